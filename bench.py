@@ -1,0 +1,216 @@
+"""Throughput benchmark: rendered env-steps/s of the batched step + raycast render.
+
+Headline workload: 4096 envs, 16x16 seeded mazes with loops, 8 wall colours,
+goal billboard, 6 uniform-random actions, 64x64 RGB frames, 512-step episodes
+with auto-reset.  Warm-up steps are untimed; the timed region runs K steps with
+every frame written into a 128-slot rollout ring (6.4 GB), so the 256 MB
+last-level cache cannot absorb the observation writes.  Inputs (maps, state,
+actions) are resident in HBM before timing starts.
+
+    python bench.py [--steps K] [--warmup W] [--form graph|eager|persistent]
+
+Prints one JSON line.  Only N = 1 GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+RING = 128
+
+
+def algorithmic_bytes(cfg: dict) -> dict:
+    """HBM bytes one env-step must move at minimum (per env)."""
+    N = cfg["side"]
+    obs = cfg["obs_h"] * cfg["obs_w"] * 3
+    map_read = (N * N + 15) // 16 * 16
+    # x y theta t episode goal door key (8 x 4) + decor (8) + flags, n_decor (2)
+    # + seed (8) + cfg index, map offset (8) + frame offset (8) + action (1)
+    state_read = 32 + 8 + 2 + 8 + 8 + 8 + 1
+    # x y theta t episode goal door key (32) + decor (8) + flags, n_decor, events (3)
+    # + reward (4) + done (1)
+    state_write = 32 + 8 + 3 + 4 + 1
+    return {"obs": obs, "map": map_read, "state_read": state_read, "state_write": state_write,
+            "total": obs + map_read + state_read + state_write}
+
+
+def _oracle_chunk(args):
+    cfg_d, seeds, acts = args
+    import oracle
+    c = oracle.make_cfg(cfg_d)
+    done, _ = oracle.rollout(c, seeds, acts)
+    return done
+
+
+def cpu_baseline(wl: dict, envs_per_worker: int = 64, steps: int = 1000) -> dict:
+    """The oracle as it stands, on the host cores: one pinned core, then every
+    core of this process's affinity set."""
+    import oracle
+    oracle.build()
+    cfg = wl["cfg"]
+    cores = sorted(os.sched_getaffinity(0))
+    n_workers = min(len(cores), 16)
+    seeds = W.seeds(wl["number"], envs_per_worker * n_workers)
+    acts = W.actions(wl["number"], steps, envs_per_worker * n_workers, cfg["n_actions"])
+    # one core
+    prev = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {cores[0]})
+    t0 = time.perf_counter()
+    one = _oracle_chunk((cfg, seeds[:envs_per_worker], np.ascontiguousarray(acts[:, :envs_per_worker])))
+    dt1 = time.perf_counter() - t0
+    os.sched_setaffinity(0, prev)
+    # all cores
+    chunks = [(cfg, seeds[k * envs_per_worker:(k + 1) * envs_per_worker],
+               np.ascontiguousarray(acts[:, k * envs_per_worker:(k + 1) * envs_per_worker]))
+              for k in range(n_workers)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(n_workers) as pool:
+        pool.map(_oracle_chunk, chunks[:1])          # start-up outside the timing
+        t0 = time.perf_counter()
+        tot = sum(pool.map(_oracle_chunk, chunks))
+        dtn = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": tot / dtn, "unit": "env-steps/s", "cores": n_workers, "kind": "oracle",
+            "sample": (f"{wl['name']}: {envs_per_worker} envs x {steps} steps per worker "
+                       f"(step + full render, FP64 C oracle, gcc -O2); one pinned core: "
+                       f"{one / dt1:.0f} env-steps/s; cpu: {model}"),
+            "one_core": one / dt1}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10_000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--form", choices=["graph", "eager", "persistent"], default="graph")
+    ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0: default)")
+    ap.add_argument("--store", type=int, default=-1, help="0 normal, 1 non-temporal (-1: default)")
+    ap.add_argument("--single-slot", action="store_true", help="write every frame to one slot")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); envs shard "
+              "independently across GPUs, see DESIGN.md", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2605_19926_amd import jx
+
+    wl = W.SCALE
+    cfg, n = wl["cfg"], wl["n_envs"]
+    K, Wu = args.steps, args.warmup
+    seeds = W.seeds(wl["number"], n)
+    env = jx.Env(seeds, cfg)
+    env.reset()
+    ob = env.obs_bytes
+    slots = 1 if args.single_slot else RING
+    obs = torch.empty(slots * ob, dtype=torch.uint8, device=env.dev)
+    env.reset(obs[:ob])
+    acts = torch.from_numpy(W.actions(wl["number"], Wu + K, n, cfg["n_actions"])).to(env.dev)
+    rew = torch.empty(RING * n, dtype=torch.float32, device=env.dev)
+    done = torch.empty(RING * n, dtype=torch.uint8, device=env.dev)
+    launch = {"form": jx.JX_FORM_PERSISTENT if args.form == "persistent" else jx.JX_FORM_PLAIN,
+              "waves_per_group": args.waves or (2 if args.form == "persistent" else 1),
+              "groups_per_cu": 4, "store_mode": max(args.store, 0)}
+    env.set_launch(**launch)
+    if args.autotune:
+        launch = env.autotune(acts, 20, obs[:ob])
+    def plan(first: int, count: int):
+        t, end, out = first, first + count, []
+        while t < end:
+            slot = t % RING
+            chunk = min(RING - slot, end - t)
+            out.append((t, slot, chunk))
+            t += chunk
+        return out
+
+    def run(first: int, count: int):
+        for t, slot, chunk in plan(first, count):
+            if args.form == "eager":
+                for k in range(chunk):
+                    s = slot + k
+                    o = obs[s * ob:(s + 1) * ob] if slots > 1 else obs
+                    env.step(acts[t + k], o, rew[s * n:(s + 1) * n], done[s * n:(s + 1) * n])
+            else:
+                o = obs[slot * ob:] if slots > 1 else obs
+                env.rollout(acts[t:t + chunk], o, rew[slot * n:], done[slot * n:], chunk,
+                            obs_stride=ob if slots > 1 else 0, graph=True)
+
+    # capture every graph length the timed region will use before timing
+    if args.form != "eager":
+        for T in sorted({c for _, _, c in plan(Wu, K)}):
+            env.rollout(acts[:T], obs, rew, done, T, obs_stride=ob if slots > 1 else 0, graph=True)
+    run(0, Wu)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    run(Wu, K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    sec = ms / 1e3
+    rate = n * K / sec
+    ab = algorithmic_bytes(cfg)
+    per_launch = ab["total"] * n
+    kern_s = sec / K
+    achieved = per_launch / kern_s / 1e9
+    S = env.get_state()
+    line = {
+        "metric": "rendered env-steps/s @4096 envs 64x64 RGB; served p50/p99 step latency vs plain",
+        "value": rate,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wu,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+u8",
+        "data": "synthetic: seeded DFS mazes, uniform random actions",
+        "config": {"workload": wl["name"], "n_envs": n, "map_side": cfg["side"],
+                   "obs": f"{cfg['obs_h']}x{cfg['obs_w']}x3 uint8", "episode_cap": cfg["episode_cap"],
+                   "form": args.form, "launch": launch,
+                   "obs_ring_slots": slots, "global_batch": n},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_env_step": ab["total"], "obs_bytes_per_env_step": ab["obs"],
+                     "kernel_avg_us": kern_s * 1e6},
+        "obs_write_gbs": ab["obs"] * n / kern_s / 1e9,
+        "episodes_completed": int(S["episode"].astype(np.int64).sum()),
+        "wall_s": wall,
+    }
+    env.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

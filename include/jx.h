@@ -1,0 +1,243 @@
+/*
+ * jx.h -- C-ABI of libjx: batched first-person grid-world environments with a
+ * raycast renderer, running as hand-written HIP kernels on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The method (JAXenstein, Tao & Konidaris): every environment is a partially
+ * observable first-person task on a tile map with discrete actions and pixel
+ * observations (abstract, Sec. 1, Sec. 3.3).  Each frame is drawn by casting one
+ * ray per image column to its first wall, found by DDA marching along tile
+ * boundaries (Sec. 2.1), over a tile-map world (Sec. 2.2, Sec. 3.2, Table 2);
+ * objects are fixed billboard sprites (Fig. 1).  Frames are rendered natively
+ * at the training resolution (Sec. 3.1, App. A.1).  Environments are stepped in
+ * batches (Sec. 1, Sec. 3.1); here a batch is one kernel launch.
+ *
+ * Conventions used by every entry point
+ *   - All functions returning jx_status return JX_OK (0) or a negative code;
+ *     jx_last_error() then holds a message (thread-local).
+ *   - "_dev" pointers are device (HBM) addresses on the context's device, owned
+ *     by the caller; "_host" pointers are host memory owned by the caller.
+ *   - Step, render and rollout are asynchronous on the context's stream and
+ *     return after enqueueing; device faults surface as JX_EDEVICE on a later
+ *     call or on jx_sync().  A context serves one stream and is not thread-safe.
+ *   - Observations are uint8 RGB, row-major [row][col][channel], row 0 at the
+ *     top.  With one configuration for all envs the batch is [n][H][W][3]; with
+ *     several configurations env i starts at byte offset jx_obs_offsets()[i].
+ *   - Reward is float32 per env, done is uint8 per env; both belong to the
+ *     transition.  When done = 1 the env has been reset inside the step and its
+ *     observation is the first frame of the next episode.
+ */
+#ifndef JX_H
+#define JX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JX_ABI_VERSION 1
+
+typedef int32_t jx_status;
+#define JX_OK 0
+#define JX_EINVAL (-1)   /* bad argument */
+#define JX_ENOMEM (-2)   /* workspace or budget too small */
+#define JX_EDEVICE (-3)  /* HIP runtime or device error */
+#define JX_ESTATE (-4)   /* call not valid in the current state (e.g. step before reset) */
+#define JX_EBUSY (-5)    /* serving: not admitted yet / result not ready */
+
+/* Per-environment configuration.  Limits: side 5..64 (tile-grid side N),
+ * n_colors 1..8, loop_frac 0..1, max_decor 0..2, obs_h even and 2..128,
+ * obs_w a multiple of 4 in 4..128, n_actions 4 or 6, episode_cap >= 1.
+ * Values used by the workloads: fov 60, move 0.1, turn pi/16, pickup 0.3. */
+typedef struct {
+  int32_t side;          /* N: the map is N x N tiles, border tiles are walls */
+  int32_t n_colors;      /* K: wall colour = palette[tile id mod K] */
+  float loop_frac;       /* fraction of standing maze separator walls removed */
+  int32_t key_door;      /* 1: a locked door and its key are placed per episode */
+  int32_t goal_sprite;   /* 1: the goal is drawn as a billboard sprite */
+  int32_t max_decor;     /* 0..2 decorative sprites per episode */
+  int32_t obs_h, obs_w;  /* frame height and width in pixels */
+  float fov_deg;         /* horizontal field of view */
+  int32_t n_actions;     /* 4: fwd, back, turn-L, turn-R; 6: fwd, back, strafe-L, strafe-R, turn-L, turn-R */
+  int32_t episode_cap;   /* truncation length in steps */
+  float move;            /* distance per move action, tiles */
+  float turn;            /* radians per turn action */
+  float pickup_radius;   /* key pickup radius, tiles */
+  float r_goal, r_key;   /* rewards */
+} jx_env_cfg;
+
+typedef struct jx_ctx jx_ctx;
+
+/* Launch mapping (results are bit-identical under every mapping). */
+#define JX_FORM_PLAIN 0       /* one wave per env, one workgroup slot per env */
+#define JX_FORM_PERSISTENT 1  /* persistent waves pull envs from a device work queue */
+typedef struct {
+  int32_t form;            /* JX_FORM_PLAIN or JX_FORM_PERSISTENT */
+  int32_t waves_per_group; /* 1, 2, 4 or 8 waves (envs in flight) per workgroup */
+  int32_t groups_per_cu;   /* persistent form: workgroups launched per compute unit, 1..16 */
+  int32_t store_mode;      /* 0: ordinary stores, 1: non-temporal observation stores */
+} jx_launch;
+
+/* Per-column record of the last render (tests and tools).  hit = tile id of the
+ * first blocking tile, side 0 = x-face (vertical grid line), 1 = y-face,
+ * t = perpendicular distance, cell = 1 wall, 2 locked door. */
+typedef struct {
+  int32_t hit;
+  int32_t side;
+  float t;
+  int32_t cell;
+} jx_col_debug;
+
+/* One named array of the state image returned by jx_get_state(). */
+typedef struct {
+  char name[24];
+  int64_t offset;   /* byte offset in the state image */
+  int64_t bytes;    /* size in bytes */
+  int32_t elem;     /* element size in bytes */
+  int32_t count;    /* number of elements */
+} jx_field;
+
+int32_t jx_abi_version(void);
+const char* jx_last_error(void);
+
+/* Bytes of device workspace needed for n_envs environments.  cfg_index[i]
+ * selects cfgs[cfg_index[i]]; cfg_index may be NULL when n_cfgs == 1.
+ * Returns 0 on invalid arguments. */
+size_t jx_workspace_bytes(int32_t n_envs, const jx_env_cfg* cfgs, int32_t n_cfgs,
+                          const int32_t* cfg_index);
+
+/* Creates a context on `device`, enqueueing on `hip_stream` (a hipStream_t;
+ * NULL = the default stream).  `workspace_dev` is caller-owned device memory of
+ * ws_bytes bytes, 256-byte aligned; it holds all environment state (SoA), maps
+ * and tables and must outlive the context. */
+jx_status jx_create(jx_ctx** out, int32_t device, void* hip_stream, void* workspace_dev,
+                    size_t ws_bytes);
+void jx_destroy(jx_ctx* ctx);
+
+/* Starts episode 0 of every env: generates each env's maze from seeds_host[i]
+ * on the host, uploads maps and tables, and runs the episode reset on the
+ * device.  When obs_dev is not NULL the first frames are rendered into it.
+ * n_envs may be 0 (every later call is then a no-op).  Synchronous: returns
+ * after the reset kernel has finished. */
+jx_status jx_reset(jx_ctx* ctx, int32_t n_envs, const uint64_t* seeds_host,
+                   const jx_env_cfg* cfgs_host, int32_t n_cfgs, const int32_t* cfg_index_host,
+                   uint8_t* obs_dev);
+
+int32_t jx_num_envs(const jx_ctx* ctx);
+/* Total observation bytes of one step (sum over envs). */
+int64_t jx_obs_bytes(const jx_ctx* ctx);
+/* offsets_host[0..n]: byte offset of env i's frame in a step's observation
+ * buffer; offsets_host[n] = jx_obs_bytes(). */
+jx_status jx_obs_offsets(const jx_ctx* ctx, int64_t* offsets_host);
+
+/* One batched transition and render.  actions_dev[n] uint8 (values >= n_actions
+ * are counted no-ops); obs_dev receives jx_obs_bytes() bytes (4-byte aligned);
+ * reward_dev[n] float32; done_dev[n] uint8. */
+jx_status jx_step(jx_ctx* ctx, const uint8_t* actions_dev, uint8_t* obs_dev, float* reward_dev,
+                  uint8_t* done_dev);
+
+/* T consecutive steps.  actions_dev[T][n]; step t writes its frames at
+ * obs_dev + t*obs_stride (obs_stride >= jx_obs_bytes(), or 0 to write every
+ * step into the same frame buffer), rewards at reward_dev + t*n, dones at
+ * done_dev + t*n.  flags & JX_ROLLOUT_GRAPH: the T launches are captured once
+ * per (T, launch mapping) into a hipGraph and replayed with one graph launch;
+ * the buffers of each call reach the captured kernels through a descriptor in
+ * the workspace, so a captured graph serves any buffers.  Without the flag the
+ * T launches are enqueued one by one. */
+#define JX_ROLLOUT_GRAPH 1
+jx_status jx_rollout(jx_ctx* ctx, int32_t T, const uint8_t* actions_dev, uint8_t* obs_dev,
+                     int64_t obs_stride, float* reward_dev, uint8_t* done_dev, int32_t flags);
+
+/* Renders the current state without stepping.  obs_dev may be NULL;
+ * column_debug_dev (nullable) receives jx_col_debug[n][max obs_w]. */
+jx_status jx_render(jx_ctx* ctx, uint8_t* obs_dev, jx_col_debug* column_debug_dev);
+
+/* State image: every per-env array, the maps and the configuration table, as
+ * one host buffer of jx_state_bytes() bytes.  jx_set_state() accepts only an
+ * image taken from a context reset with the same envs and configurations.
+ * Both synchronise the context's stream. */
+size_t jx_state_bytes(const jx_ctx* ctx);
+jx_status jx_state_layout(const jx_ctx* ctx, jx_field* fields, int32_t cap, int32_t* n_fields);
+jx_status jx_get_state(const jx_ctx* ctx, void* host_buf, size_t bytes);
+jx_status jx_set_state(jx_ctx* ctx, const void* host_buf, size_t bytes);
+
+jx_status jx_set_launch(jx_ctx* ctx, const jx_launch* launch);
+jx_status jx_get_launch(const jx_ctx* ctx, jx_launch* launch);
+
+/* Autotuner: times every candidate mapping over `iters` steps driven by
+ * actions_dev[iters][n], writing frames into obs_scratch_dev (jx_obs_bytes()
+ * bytes), checks that each candidate's frames, rewards, dones and state are
+ * bit-identical to the default mapping's, and selects the fastest.  The env
+ * state is restored afterwards.  cache_path (nullable) is a text file of
+ * previous choices keyed by device and workload shape.  *chosen (nullable)
+ * receives the pick.  Synchronous. */
+jx_status jx_autotune(jx_ctx* ctx, const uint8_t* actions_dev, int32_t iters,
+                      uint8_t* obs_scratch_dev, const char* cache_path, jx_launch* chosen);
+
+jx_status jx_sync(jx_ctx* ctx);
+
+/* Host only (no device): the N x N tile grid (0 floor, 1 wall) that jx_reset
+ * builds for `seed` under `cfg`. */
+jx_status jx_make_layout(uint64_t seed, const jx_env_cfg* cfg, uint8_t* grid_host);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop holding many clients' environments resident on one
+ * device.  Clients open env batches of any size and configuration; requests
+ * (one step of one client) that are ready are coalesced into shared persistent
+ * launches spread over n_streams streams, so that requests arriving while
+ * others run are admitted and overlap on the device (continuous batching).
+ * Clients are admitted while their device memory fits the HBM budget; others
+ * wait in FIFO order.  All functions are thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct jx_server jx_server;
+
+#define JX_SERVE_COALESCE 0  /* mode: coalesce ready requests into shared launches */
+#define JX_SERVE_PLAIN 1     /* mode: one launch per request, FIFO, one stream */
+
+/* hbm_budget_bytes bounds the device memory of admitted clients' state, maps
+ * and I/O buffers.  n_streams 1..8.  max_batch_envs bounds envs per launch
+ * (0 = no bound). */
+jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_bytes,
+                           int32_t n_streams, int32_t mode, int32_t max_batch_envs);
+void jx_server_destroy(jx_server* srv);
+
+/* Opens a client of n_envs envs (one configuration for all).  Returns JX_OK
+ * when admitted, JX_EBUSY when queued for admission (the id is valid either
+ * way; requests submitted meanwhile wait), JX_ENOMEM when the client alone
+ * exceeds the budget. */
+jx_status jx_server_open(jx_server* srv, int32_t n_envs, const uint64_t* seeds_host,
+                         const jx_env_cfg* cfg, int32_t* client);
+
+/* Queues one step of `client` with actions_host[n_envs] (copied).  *ticket
+ * identifies the request. */
+jx_status jx_server_submit(jx_server* srv, int32_t client, const uint8_t* actions_host,
+                           uint64_t* ticket);
+
+/* Waits for a request (timeout_s < 0: forever; 0: poll, JX_EBUSY if not done)
+ * and copies its frames (n_envs * H * W * 3 bytes), rewards and dones into
+ * host buffers (each nullable).  latency_s (nullable) = submit-to-complete
+ * seconds. */
+jx_status jx_server_wait(jx_server* srv, uint64_t ticket, double timeout_s, uint8_t* obs_host,
+                         float* reward_host, uint8_t* done_host, double* latency_s);
+
+/* Releases the client once its queued requests have completed. */
+jx_status jx_server_close(jx_server* srv, int32_t client);
+
+/* Counters: launches, requests, envs stepped, admission waits, bytes in use. */
+typedef struct {
+  int64_t launches;
+  int64_t requests;
+  int64_t env_steps;
+  int64_t admission_waits;
+  int64_t bytes_in_use;
+  int64_t clients_active;
+  int64_t clients_pending;
+} jx_server_stats;
+jx_status jx_server_get_stats(jx_server* srv, jx_server_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JX_H */

@@ -120,6 +120,8 @@ def lib():
                                ctypes.POINTER(OrcState), ctypes.c_int32,
                                ctypes.POINTER(OrcState), f64p, i32p, i32p, i32p]
         L.orc_step.restype = ctypes.c_int32
+        L.orc_step_w.argtypes = L.orc_step.argtypes + [ctypes.c_double]
+        L.orc_step_w.restype = ctypes.c_int32
         L.orc_render.argtypes = [u8p, ctypes.POINTER(OrcCfg), ctypes.POINTER(OrcState), u8p,
                                  i32p, i32p, f64p, i32p, i32p, i32p, f64p]
         L.orc_render.restype = ctypes.c_int32
@@ -179,15 +181,17 @@ def reset(grid: np.ndarray, cfg: OrcCfg, seed: int, episode: int) -> OrcState:
     return out
 
 
-def step(grid: np.ndarray, cfg: OrcCfg, seed: int, state: OrcState, action: int):
-    """Returns (next_state, reward, done, events, step_flags)."""
+def step(grid: np.ndarray, cfg: OrcCfg, seed: int, state: OrcState, action: int,
+         window: float = 1e-5):
+    """Returns (next_state, reward, done, events, step_flags); the step flags
+    mark decisions within `window` of their boundary."""
     g = np.ascontiguousarray(grid, np.uint8)
     out = OrcState()
     r = ctypes.c_double()
     d, ev, sf = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    rc = lib().orc_step(_p(g, ctypes.c_uint8), ctypes.byref(cfg), seed & (2**64 - 1),
-                        ctypes.byref(state), int(action), ctypes.byref(out), ctypes.byref(r),
-                        ctypes.byref(d), ctypes.byref(ev), ctypes.byref(sf))
+    rc = lib().orc_step_w(_p(g, ctypes.c_uint8), ctypes.byref(cfg), seed & (2**64 - 1),
+                          ctypes.byref(state), int(action), ctypes.byref(out), ctypes.byref(r),
+                          ctypes.byref(d), ctypes.byref(ev), ctypes.byref(sf), float(window))
     if rc != 0:
         raise ValueError("step failed")
     return out, r.value, d.value, ev.value, sf.value

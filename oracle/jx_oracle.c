@@ -272,12 +272,12 @@ static int near_int(double v, double w) { return fabs(v - floor(v + 0.5)) <= w; 
 /* r_goal, terminal); truncation when t+1 reaches the cap; done resets the    */
 /* episode in place and the returned state is the next episode's first.       */
 /* ------------------------------------------------------------------------ */
-int32_t orc_step(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, const orc_state* in,
-                 int32_t action, orc_state* out, double* reward, int32_t* done, int32_t* events,
-                 int32_t* sflags) {
+int32_t orc_step_w(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, const orc_state* in,
+                   int32_t action, orc_state* out, double* reward, int32_t* done, int32_t* events,
+                   int32_t* sflags, double window) {
   if (!grid || !cfg || !in || !out) return -1;
   const int32_t N = cfg->side;
-  const double W5 = 1e-5;
+  const double W5 = window;
   int32_t ev = 0, sf = 0;
   double r = 0.0;
   double th = in->theta;
@@ -382,6 +382,12 @@ int32_t orc_step(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, const o
   if (events) *events = ev;
   if (sflags) *sflags = sf;
   return 0;
+}
+
+int32_t orc_step(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, const orc_state* in,
+                 int32_t action, orc_state* out, double* reward, int32_t* done, int32_t* events,
+                 int32_t* sflags) {
+  return orc_step_w(grid, cfg, seed, in, action, out, reward, done, events, sflags, 1e-5);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -98,6 +98,13 @@ int32_t orc_step(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed,
                  const orc_state* in, int32_t action, orc_state* out,
                  double* reward, int32_t* done, int32_t* events, int32_t* sflags);
 
+/* Same transition; the step flags use `window` instead of 1e-5 (for comparing
+ * trajectories whose positions have drifted apart by rounding). */
+int32_t orc_step_w(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed,
+                   const orc_state* in, int32_t action, orc_state* out,
+                   double* reward, int32_t* done, int32_t* events, int32_t* sflags,
+                   double window);
+
 /* ---- render ------------------------------------------------------------ */
 /* Renders `st` into obs[H][W][3].  Per column: hit tile id, side (0: x-face,
  * 1: y-face), perpendicular distance, flags, and the alternative (hit, side,

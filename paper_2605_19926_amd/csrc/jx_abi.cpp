@@ -1,0 +1,755 @@
+// jx_abi.cpp -- host runtime behind include/jx.h: validation, workspace layout,
+// reset (host maze generation + device episode reset), step, hipGraph rollouts,
+// state import/export and the launch-mapping autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <array>
+#include <fstream>
+#include <map>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "jx.h"
+#include "jx_common.h"
+#include "jx_internal.h"
+#include "jx_layout.h"
+
+using namespace jx;
+
+struct jx_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  uint8_t* ws = nullptr;
+  size_t ws_bytes = 0;
+  int n = -1;  // -1 until reset
+  Layout L{};
+  DevState S{};
+  std::vector<jx_env_cfg> cfgs;
+  std::vector<int32_t> cfg_idx;
+  std::vector<int64_t> obs_off;
+  std::vector<DevCfg> dev_cfgs;
+  int max_side = 0, max_w = 0;
+  int n_cu = 1;
+  LaunchCfg launch{0, 1, 4, 0};
+  // captured rollouts, keyed by (T, launch mapping)
+  std::map<std::array<int32_t, 5>, hipGraphExec_t> graphs;
+};
+
+namespace jx {
+
+thread_local std::string g_last_error;
+
+jx_status set_error(jx_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+bool validate_cfg(const jx_env_cfg& c, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (c.side < 5 || c.side > kMaxSide) return bad("side must be in 5..64");
+  if (c.n_colors < 1 || c.n_colors > 8) return bad("n_colors must be in 1..8");
+  if (!(c.loop_frac >= 0.f && c.loop_frac <= 1.f)) return bad("loop_frac must be in [0, 1]");
+  if (c.key_door != 0 && c.key_door != 1) return bad("key_door must be 0 or 1");
+  if (c.goal_sprite != 0 && c.goal_sprite != 1) return bad("goal_sprite must be 0 or 1");
+  if (c.max_decor < 0 || c.max_decor > kMaxDecor) return bad("max_decor must be in 0..2");
+  if (c.obs_h < 2 || c.obs_h > kMaxH || (c.obs_h & 1)) return bad("obs_h must be even, 2..128");
+  if (c.obs_w < 4 || c.obs_w > kMaxW || (c.obs_w & 3)) return bad("obs_w must be a multiple of 4, 4..128");
+  if (!(c.fov_deg >= 0.f && c.fov_deg < 180.f)) return bad("fov_deg must be in [0, 180)");
+  if (c.n_actions != 4 && c.n_actions != 6) return bad("n_actions must be 4 or 6");
+  if (c.episode_cap < 1) return bad("episode_cap must be >= 1");
+  if (!std::isfinite(c.move) || !std::isfinite(c.turn) || !std::isfinite(c.r_goal) ||
+      !std::isfinite(c.r_key) || !(c.pickup_radius >= 0.f) || !std::isfinite(c.pickup_radius))
+    return bad("move, turn, rewards and pickup_radius must be finite (radius >= 0)");
+  if (std::fabs(c.move) >= 1.f) return bad("|move| must be below one tile");
+  return true;
+}
+
+DevCfg derive_cfg(const jx_env_cfg& c) {
+  DevCfg d{};
+  d.side = c.side;
+  d.n_colors = c.n_colors;
+  d.key_door = c.key_door;
+  d.goal_sprite = c.goal_sprite;
+  d.max_decor = c.max_decor;
+  d.obs_h = c.obs_h;
+  d.obs_w = c.obs_w;
+  d.n_actions = c.n_actions;
+  d.cap = c.episode_cap;
+  d.move = c.move;
+  d.turn = c.turn;
+  d.pr2 = c.pickup_radius * c.pickup_radius;
+  d.r_goal = c.r_goal;
+  d.r_key = c.r_key;
+  d.tanH = (float)std::tan((double)c.fov_deg * M_PI / 360.0);
+  return d;
+}
+
+static int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+Layout make_layout(int n, int n_cfgs, int64_t maps_bytes) {
+  Layout L{};
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  const int64_t nn = std::max(n, 1);
+  L.hdr = take(sizeof(WsHeader));
+  L.x = take(4 * nn);
+  L.y = take(4 * nn);
+  L.th = take(4 * nn);
+  L.t = take(4 * nn);
+  L.ep = take(4 * nn);
+  L.goal = take(4 * nn);
+  L.door = take(4 * nn);
+  L.key = take(4 * nn);
+  L.decor = take(8 * nn);
+  L.flags = take(nn);
+  L.events = take(nn);
+  L.ndecor = take(nn);
+  L.invalid = take(4 * nn);
+  L.seed = take(8 * nn);
+  L.cfg_idx = take(4 * nn);
+  L.map_off = take(4 * nn);
+  L.obs_off = take(8 * (nn + 1));
+  L.order = take(4 * nn);
+  L.cfgs = take((int64_t)sizeof(DevCfg) * std::max(n_cfgs, 1));
+  L.maps = take(std::max<int64_t>(maps_bytes, 16));
+  // after the state image: the rollout descriptor (scratch, not state)
+  L.rdesc = take(sizeof(RolloutDesc));
+  L.total = o;
+  return L;
+}
+
+int64_t map_bytes_of(int side) { return align_up((int64_t)side * side, 16); }
+
+DevState bind_state(uint8_t* ws, const Layout& L, int n) {
+  DevState s{};
+  s.x = (float*)(ws + L.x);
+  s.y = (float*)(ws + L.y);
+  s.th = (float*)(ws + L.th);
+  s.t = (uint32_t*)(ws + L.t);
+  s.ep = (uint32_t*)(ws + L.ep);
+  s.goal = (int32_t*)(ws + L.goal);
+  s.door = (int32_t*)(ws + L.door);
+  s.key = (int32_t*)(ws + L.key);
+  s.decor = (int32_t*)(ws + L.decor);
+  s.flags = ws + L.flags;
+  s.events = ws + L.events;
+  s.ndecor = ws + L.ndecor;
+  s.invalid = (uint32_t*)(ws + L.invalid);
+  s.seed = (const uint64_t*)(ws + L.seed);
+  s.cfg_idx = (const int32_t*)(ws + L.cfg_idx);
+  s.map_off = (const uint32_t*)(ws + L.map_off);
+  s.obs_off = (const int64_t*)(ws + L.obs_off);
+  s.order = (const int32_t*)(ws + L.order);
+  s.rdesc = (RolloutDesc*)(ws + L.rdesc);
+  s.cfgs = (const DevCfg*)(ws + L.cfgs);
+  s.maps = ws + L.maps;
+  s.hdr = (WsHeader*)(ws + L.hdr);
+  s.n = n;
+  return s;
+}
+
+// Builds the host image of a freshly reset workspace (state arrays zero; the
+// device episode reset fills them).  Maze generation is spread over threads.
+jx_status build_image(int n, const uint64_t* seeds, const jx_env_cfg* cfgs, int n_cfgs,
+                      const int32_t* cfg_index, std::vector<uint8_t>* img, Layout* Lout,
+                      std::vector<int64_t>* obs_off, std::vector<int32_t>* idx_out) {
+  std::vector<int32_t> idx(n);
+  for (int i = 0; i < n; ++i) {
+    int c = cfg_index ? cfg_index[i] : 0;
+    if (c < 0 || c >= n_cfgs) return set_error(JX_EINVAL, "cfg_index out of range");
+    idx[i] = c;
+  }
+  std::vector<uint32_t> moff(n);
+  int64_t mb = 0;
+  for (int i = 0; i < n; ++i) {
+    if (mb > 0xFFFFFFFFll) return set_error(JX_ENOMEM, "maps exceed 4 GiB");
+    moff[i] = (uint32_t)mb;
+    mb += map_bytes_of(cfgs[idx[i]].side);
+  }
+  Layout L = make_layout(n, n_cfgs, mb);
+  img->assign((size_t)L.total, 0);
+  uint8_t* b = img->data();
+  WsHeader* h = (WsHeader*)(b + L.hdr);
+  h->magic = kStateMagic;
+  h->n_envs = n;
+  h->state_bytes = L.rdesc;
+  h->n_cfgs = n_cfgs;
+  obs_off->assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const jx_env_cfg& c = cfgs[idx[i]];
+    (*obs_off)[i + 1] = (*obs_off)[i] + (int64_t)c.obs_h * c.obs_w * 3;
+  }
+  std::memcpy(b + L.seed, seeds, 8 * (size_t)n);
+  std::memcpy(b + L.cfg_idx, idx.data(), 4 * (size_t)n);
+  std::memcpy(b + L.map_off, moff.data(), 4 * (size_t)n);
+  std::memcpy(b + L.obs_off, obs_off->data(), 8 * (size_t)(n + 1));
+  for (int i = 0; i < n; ++i) ((int32_t*)(b + L.decor))[2 * i] = ((int32_t*)(b + L.decor))[2 * i + 1] = -1;
+  // costliest envs first for the persistent queue (frame bytes, then map side)
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    const jx_env_cfg& A = cfgs[idx[a]];
+    const jx_env_cfg& C = cfgs[idx[c]];
+    int64_t ca = (int64_t)A.obs_h * A.obs_w * 4 + (int64_t)A.side * A.side;
+    int64_t cc = (int64_t)C.obs_h * C.obs_w * 4 + (int64_t)C.side * C.side;
+    return ca > cc;
+  });
+  std::memcpy(b + L.order, order.data(), 4 * (size_t)n);
+  for (int c = 0; c < n_cfgs; ++c) ((DevCfg*)(b + L.cfgs))[c] = derive_cfg(cfgs[c]);
+  // mazes
+  unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int n_thr = (n >= 256) ? (int)hw : 1;
+  std::vector<std::thread> thr;
+  std::vector<int> okv(n_thr, 1);
+  for (int tI = 0; tI < n_thr; ++tI) {
+    thr.emplace_back([&, tI] {
+      for (int i = tI; i < n; i += n_thr) {
+        const jx_env_cfg& c = cfgs[idx[i]];
+        if (!make_maze(seeds[i], c.side, c.loop_frac, b + L.maps + moff[i])) okv[tI] = 0;
+      }
+    });
+  }
+  for (auto& t : thr) t.join();
+  for (int v : okv)
+    if (!v) return set_error(JX_EINVAL, "maze generation failed");
+  *Lout = L;
+  *idx_out = idx;
+  return JX_OK;
+}
+
+}  // namespace jx
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return set_error(JX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static jx_status launch_or_fail(jx_ctx* c, const DevIo& io, hipStream_t st,
+                                const RolloutDesc* rd = nullptr, int t = 0) {
+  int rc = launch_batch(c->S, io, rd, t, c->launch, c->max_side, c->n_cu, st);
+  if (rc != 0) return set_error(JX_EDEVICE, std::string("kernel launch: ") + kernel_error_string(rc));
+  return JX_OK;
+}
+
+static jx_status check_ready(const jx_ctx* c) {
+  if (!c) return set_error(JX_EINVAL, "null context");
+  if (c->n < 0) return set_error(JX_ESTATE, "context not reset");
+  return JX_OK;
+}
+
+extern "C" {
+
+int32_t jx_abi_version(void) { return JX_ABI_VERSION; }
+
+const char* jx_last_error(void) { return g_last_error.c_str(); }
+
+size_t jx_workspace_bytes(int32_t n_envs, const jx_env_cfg* cfgs, int32_t n_cfgs,
+                          const int32_t* cfg_index) {
+  if (n_envs < 0 || !cfgs || n_cfgs < 1 || (n_cfgs > 1 && !cfg_index && n_envs > 0)) return 0;
+  int64_t mb = 0;
+  for (int i = 0; i < n_envs; ++i) {
+    int c = cfg_index ? cfg_index[i] : 0;
+    if (c < 0 || c >= n_cfgs) return 0;
+    if (cfgs[c].side < 5 || cfgs[c].side > kMaxSide) return 0;
+    mb += map_bytes_of(cfgs[c].side);
+  }
+  return (size_t)make_layout(n_envs, n_cfgs, mb).total;
+}
+
+jx_status jx_create(jx_ctx** out, int32_t device, void* hip_stream, void* workspace_dev,
+                    size_t ws_bytes) {
+  if (!out) return set_error(JX_EINVAL, "out is null");
+  *out = nullptr;
+  if (!workspace_dev) return set_error(JX_EINVAL, "workspace is null");
+  if (((uintptr_t)workspace_dev & 255) != 0) return set_error(JX_EINVAL, "workspace must be 256-byte aligned");
+  int n_dev = 0;
+  HIPCHK(hipGetDeviceCount(&n_dev));
+  if (device < 0 || device >= n_dev) return set_error(JX_EINVAL, "bad device index");
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  jx_ctx* c = new jx_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (uint8_t*)workspace_dev;
+  c->ws_bytes = ws_bytes;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return set_error(JX_EDEVICE, "stream creation failed");
+  }
+  *out = c;
+  return JX_OK;
+}
+
+void jx_destroy(jx_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+  delete c;
+}
+
+jx_status jx_reset(jx_ctx* c, int32_t n_envs, const uint64_t* seeds, const jx_env_cfg* cfgs,
+                   int32_t n_cfgs, const int32_t* cfg_index, uint8_t* obs_dev) {
+  if (!c) return set_error(JX_EINVAL, "null context");
+  if (n_envs < 0) return set_error(JX_EINVAL, "n_envs < 0");
+  if (!cfgs || n_cfgs < 1) return set_error(JX_EINVAL, "need at least one configuration");
+  if (n_cfgs > 1 && !cfg_index && n_envs > 0) return set_error(JX_EINVAL, "cfg_index required when n_cfgs > 1");
+  if (n_envs > 0 && !seeds) return set_error(JX_EINVAL, "seeds is null");
+  if (obs_dev && ((uintptr_t)obs_dev & 3)) return set_error(JX_EINVAL, "obs must be 4-byte aligned");
+  for (int k = 0; k < n_cfgs; ++k) {
+    std::string why;
+    if (!validate_cfg(cfgs[k], &why)) return set_error(JX_EINVAL, "cfg " + std::to_string(k) + ": " + why);
+  }
+  std::vector<uint8_t> img;
+  Layout L;
+  std::vector<int64_t> oo;
+  std::vector<int32_t> idx;
+  jx_status st = build_image(n_envs, seeds, cfgs, n_cfgs, cfg_index, &img, &L, &oo, &idx);
+  if (st != JX_OK) return st;
+  if ((size_t)L.total > c->ws_bytes)
+    return set_error(JX_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  HIPCHK(hipSetDevice(c->device));
+  for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+  HIPCHK(hipMemcpyAsync(c->ws, img.data(), (size_t)L.total, hipMemcpyHostToDevice, c->stream));
+  c->L = L;
+  c->n = n_envs;
+  c->S = bind_state(c->ws, L, n_envs);
+  c->cfgs.assign(cfgs, cfgs + n_cfgs);
+  c->cfg_idx = idx;
+  c->obs_off = oo;
+  c->dev_cfgs.clear();
+  c->max_side = 0;
+  c->max_w = 0;
+  for (int k = 0; k < n_cfgs; ++k) {
+    c->dev_cfgs.push_back(derive_cfg(cfgs[k]));
+    c->max_side = std::max(c->max_side, cfgs[k].side);
+    c->max_w = std::max(c->max_w, cfgs[k].obs_w);
+  }
+  DevIo io{};
+  io.obs = obs_dev;
+  io.mode = MODE_RESET;
+  io.store_mode = 0;
+  if (n_envs > 0) {
+    LaunchCfg keep = c->launch;
+    c->launch = LaunchCfg{0, 1, 1, 0};
+    jx_status r = launch_or_fail(c, io, c->stream);
+    c->launch = keep;
+    if (r != JX_OK) return r;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return JX_OK;
+}
+
+int32_t jx_num_envs(const jx_ctx* c) { return c ? c->n : -1; }
+
+int64_t jx_obs_bytes(const jx_ctx* c) {
+  if (!c || c->n < 0) return -1;
+  return c->obs_off.empty() ? 0 : c->obs_off.back();
+}
+
+jx_status jx_obs_offsets(const jx_ctx* c, int64_t* offsets_host) {
+  jx_status st = check_ready(c);
+  if (st) return st;
+  if (!offsets_host) return set_error(JX_EINVAL, "offsets is null");
+  std::memcpy(offsets_host, c->obs_off.data(), 8 * c->obs_off.size());
+  return JX_OK;
+}
+
+jx_status jx_step(jx_ctx* c, const uint8_t* actions, uint8_t* obs, float* reward, uint8_t* done) {
+  jx_status st = check_ready(c);
+  if (st) return st;
+  if (c->n == 0) return JX_OK;
+  if (!actions || !obs || !reward || !done) return set_error(JX_EINVAL, "null buffer");
+  if ((uintptr_t)obs & 3) return set_error(JX_EINVAL, "obs must be 4-byte aligned");
+  DevIo io{};
+  io.act = actions;
+  io.obs = obs;
+  io.rew = reward;
+  io.done = done;
+  io.mode = MODE_STEP;
+  io.store_mode = c->launch.store_mode;
+  return launch_or_fail(c, io, c->stream);
+}
+
+jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs, int64_t obs_stride,
+                     float* reward, uint8_t* done, int32_t flags) {
+  jx_status st = check_ready(c);
+  if (st) return st;
+  if (T < 0) return set_error(JX_EINVAL, "T < 0");
+  if (c->n == 0 || T == 0) return JX_OK;
+  if (!actions || !obs || !reward || !done) return set_error(JX_EINVAL, "null buffer");
+  const int64_t ob = c->obs_off.back();
+  if (obs_stride < 0 || (obs_stride != 0 && obs_stride < ob) || (obs_stride & 3) || ((uintptr_t)obs & 3))
+    return set_error(JX_EINVAL, "obs_stride must be 0 or >= jx_obs_bytes(), 4-byte aligned");
+  HIPCHK(hipSetDevice(c->device));
+  if (!(flags & JX_ROLLOUT_GRAPH)) {
+    for (int t = 0; t < T; ++t) {
+      DevIo io{};
+      io.act = actions + (int64_t)t * c->n;
+      io.obs = obs + (int64_t)t * obs_stride;
+      io.rew = reward + (int64_t)t * c->n;
+      io.done = done + (int64_t)t * c->n;
+      io.mode = MODE_STEP;
+      io.store_mode = c->launch.store_mode;
+      st = launch_or_fail(c, io, c->stream);
+      if (st) return st;
+    }
+    return JX_OK;
+  }
+  // The captured kernels read their buffers from the workspace descriptor,
+  // so one graph per (T, mapping) serves every call.
+  RolloutDesc d{actions, obs, reward, done, obs_stride, c->n, c->launch.store_mode};
+  int rc = launch_set_desc(c->S.rdesc, d, c->stream);
+  if (rc) return set_error(JX_EDEVICE, std::string("descriptor update: ") + kernel_error_string(rc));
+  const std::array<int32_t, 5> key = {T, c->launch.form, c->launch.waves_per_group,
+                                      c->launch.groups_per_cu, c->launch.store_mode};
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    jx_status lst = JX_OK;
+    DevIo io{};
+    io.mode = MODE_STEP;
+    for (int t = 0; t < T && lst == JX_OK; ++t) lst = launch_or_fail(c, io, c->cap_stream, c->S.rdesc, t);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (lst != JX_OK) {
+      if (g) hipGraphDestroy(g);
+      return lst;
+    }
+    if (e != hipSuccess) return set_error(JX_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return set_error(JX_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    if (c->graphs.size() >= 8) {
+      hipGraphExecDestroy(c->graphs.begin()->second);
+      c->graphs.erase(c->graphs.begin());
+    }
+    it = c->graphs.emplace(key, ge).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, c->stream));
+  return JX_OK;
+}
+
+jx_status jx_render(jx_ctx* c, uint8_t* obs, jx_col_debug* dbg) {
+  jx_status st = check_ready(c);
+  if (st) return st;
+  if (c->n == 0) return JX_OK;
+  if (obs && ((uintptr_t)obs & 3)) return set_error(JX_EINVAL, "obs must be 4-byte aligned");
+  DevIo io{};
+  io.obs = obs;
+  io.dbg = dbg;
+  io.dbg_stride = c->max_w;
+  io.mode = MODE_RENDER;
+  io.store_mode = c->launch.store_mode;
+  return launch_or_fail(c, io, c->stream);
+}
+
+size_t jx_state_bytes(const jx_ctx* c) {
+  if (!c || c->n < 0) return 0;
+  return (size_t)c->L.rdesc;
+}
+
+jx_status jx_state_layout(const jx_ctx* c, jx_field* f, int32_t cap, int32_t* n_fields) {
+  jx_status st = check_ready(c);
+  if (st) return st;
+  const Layout& L = c->L;
+  const int n = c->n;
+  struct F {
+    const char* name;
+    int64_t off;
+    int elem;
+    int64_t count;
+  } all[] = {{"header", L.hdr, 1, (int64_t)sizeof(WsHeader)},
+             {"x", L.x, 4, n},
+             {"y", L.y, 4, n},
+             {"theta", L.th, 4, n},
+             {"t", L.t, 4, n},
+             {"episode", L.ep, 4, n},
+             {"goal", L.goal, 4, n},
+             {"door", L.door, 4, n},
+             {"key", L.key, 4, n},
+             {"decor", L.decor, 4, 2 * (int64_t)n},
+             {"flags", L.flags, 1, n},
+             {"events", L.events, 1, n},
+             {"n_decor", L.ndecor, 1, n},
+             {"invalid", L.invalid, 4, n},
+             {"seed", L.seed, 8, n},
+             {"cfg_index", L.cfg_idx, 4, n},
+             {"map_offset", L.map_off, 4, n},
+             {"obs_offset", L.obs_off, 8, (int64_t)n + 1},
+             {"order", L.order, 4, n},
+             {"cfgs", L.cfgs, (int)sizeof(DevCfg), (int64_t)c->cfgs.size()},
+             {"maps", L.maps, 1, L.rdesc - L.maps}};
+  const int total = (int)(sizeof(all) / sizeof(all[0]));
+  if (n_fields) *n_fields = total;
+  if (!f) return JX_OK;
+  for (int i = 0; i < total && i < cap; ++i) {
+    std::memset(&f[i], 0, sizeof(jx_field));
+    std::snprintf(f[i].name, sizeof(f[i].name), "%s", all[i].name);
+    f[i].offset = all[i].off;
+    f[i].elem = all[i].elem;
+    f[i].count = (int32_t)all[i].count;
+    f[i].bytes = all[i].elem * all[i].count;
+  }
+  return JX_OK;
+}
+
+jx_status jx_get_state(const jx_ctx* c, void* host, size_t bytes) {
+  jx_status st = check_ready(c);
+  if (st) return st;
+  if (!host || bytes < (size_t)c->L.rdesc) return set_error(JX_EINVAL, "host buffer too small");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpyAsync(host, c->ws, (size_t)c->L.rdesc, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return JX_OK;
+}
+
+jx_status jx_set_state(jx_ctx* c, const void* host, size_t bytes) {
+  jx_status st = check_ready(c);
+  if (st) return st;
+  if (!host || bytes < (size_t)c->L.rdesc) return set_error(JX_EINVAL, "state image too small");
+  const uint8_t* b = (const uint8_t*)host;
+  WsHeader h;
+  std::memcpy(&h, b + c->L.hdr, sizeof(h));
+  if (h.magic != kStateMagic || h.n_envs != c->n || h.state_bytes != c->L.rdesc ||
+      h.n_cfgs != (int32_t)c->cfgs.size())
+    return set_error(JX_EINVAL, "state image does not match this context");
+  if (std::memcmp(b + c->L.cfgs, c->dev_cfgs.data(), sizeof(DevCfg) * c->dev_cfgs.size()) != 0 ||
+      std::memcmp(b + c->L.obs_off, c->obs_off.data(), 8 * c->obs_off.size()) != 0 ||
+      std::memcmp(b + c->L.cfg_idx, c->cfg_idx.data(), 4 * (size_t)c->n) != 0)
+    return set_error(JX_EINVAL, "state image configuration differs from this context");
+  // every index the kernels dereference must be in range
+  const Layout& L = c->L;
+  for (int i = 0; i < c->n; ++i) {
+    const int N = c->cfgs[c->cfg_idx[i]].side;
+    const int NN = N * N;
+    float x, y, th;
+    std::memcpy(&x, b + L.x + 4 * i, 4);
+    std::memcpy(&y, b + L.y + 4 * i, 4);
+    std::memcpy(&th, b + L.th + 4 * i, 4);
+    int32_t ids[5];
+    std::memcpy(&ids[0], b + L.goal + 4 * i, 4);
+    std::memcpy(&ids[1], b + L.door + 4 * i, 4);
+    std::memcpy(&ids[2], b + L.key + 4 * i, 4);
+    std::memcpy(&ids[3], b + L.decor + 8 * i, 8);
+    const uint8_t nd = b[L.ndecor + i];
+    uint32_t moff;
+    std::memcpy(&moff, b + L.map_off + 4 * i, 4);
+    bool ok = std::isfinite(x) && std::isfinite(y) && std::isfinite(th) && x >= 0.f && y >= 0.f &&
+              x < (float)N && y < (float)N && nd <= kMaxDecor && b[L.flags + i] <= 3 &&
+              moff + (uint64_t)NN <= (uint64_t)(L.rdesc - L.maps);
+    for (int k = 0; k < 5; ++k) ok = ok && ids[k] >= -1 && ids[k] < NN;
+    for (int k = 0; k < nd; ++k) ok = ok && ids[3 + k] >= 0;
+    if (!ok) return set_error(JX_EINVAL, "state image: env " + std::to_string(i) + " holds an out-of-range value");
+  }
+  std::vector<uint8_t> img(b, b + c->L.rdesc);
+  WsHeader* hh = (WsHeader*)(img.data() + c->L.hdr);
+  hh->queue = 0;
+  hh->exited = 0;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpyAsync(c->ws, img.data(), img.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return JX_OK;
+}
+
+jx_status jx_set_launch(jx_ctx* c, const jx_launch* l) {
+  if (!c || !l) return set_error(JX_EINVAL, "null argument");
+  const int w = l->waves_per_group;
+  if (l->form != JX_FORM_PLAIN && l->form != JX_FORM_PERSISTENT) return set_error(JX_EINVAL, "bad form");
+  if (w != 1 && w != 2 && w != 4 && w != 8) return set_error(JX_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
+  if (l->form == JX_FORM_PERSISTENT && (l->groups_per_cu < 1 || l->groups_per_cu > 16))
+    return set_error(JX_EINVAL, "groups_per_cu must be in 1..16");
+  if (l->store_mode != 0 && l->store_mode != 1) return set_error(JX_EINVAL, "store_mode must be 0 or 1");
+  c->launch = LaunchCfg{l->form, w, std::max(1, l->groups_per_cu), l->store_mode};
+  return JX_OK;
+}
+
+jx_status jx_get_launch(const jx_ctx* c, jx_launch* l) {
+  if (!c || !l) return set_error(JX_EINVAL, "null argument");
+  l->form = c->launch.form;
+  l->waves_per_group = c->launch.waves_per_group;
+  l->groups_per_cu = c->launch.groups_per_cu;
+  l->store_mode = c->launch.store_mode;
+  return JX_OK;
+}
+
+jx_status jx_sync(jx_ctx* c) {
+  if (!c) return set_error(JX_EINVAL, "null context");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipGetLastError());
+  return JX_OK;
+}
+
+jx_status jx_make_layout(uint64_t seed, const jx_env_cfg* cfg, uint8_t* grid) {
+  if (!cfg || !grid) return set_error(JX_EINVAL, "null argument");
+  std::string why;
+  if (!validate_cfg(*cfg, &why)) return set_error(JX_EINVAL, why);
+  if (!make_maze(seed, cfg->side, cfg->loop_frac, grid)) return set_error(JX_EINVAL, "maze generation failed");
+  return JX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+std::string tune_key(const jx_ctx* c) {
+  hipDeviceProp_t p;
+  hipGetDeviceProperties(&p, c->device);
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* d, size_t n) {
+    const uint8_t* b = (const uint8_t*)d;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(c->dev_cfgs.data(), sizeof(DevCfg) * c->dev_cfgs.size());
+  mix(c->cfg_idx.data(), 4 * c->cfg_idx.size());
+  std::ostringstream o;
+  o << p.gcnArchName << "/cu" << c->n_cu << "/n" << c->n << "/h" << std::hex << h;
+  std::string s = o.str();
+  for (char& ch : s)
+    if (ch == ' ' || ch == '\n') ch = '_';
+  return s;
+}
+
+bool cache_lookup(const char* path, const std::string& key, LaunchCfg* out) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string k;
+  LaunchCfg l{};
+  bool found = false;
+  while (f >> k >> l.form >> l.waves_per_group >> l.groups_per_cu >> l.store_mode)
+    if (k == key) {
+      *out = l;
+      found = true;
+    }
+  return found;
+}
+
+}  // namespace
+
+extern "C" jx_status jx_autotune(jx_ctx* c, const uint8_t* actions, int32_t iters,
+                                 uint8_t* obs_scratch, const char* cache_path, jx_launch* chosen) {
+  jx_status st = check_ready(c);
+  if (st) return st;
+  if (iters < 1 || !actions || !obs_scratch) return set_error(JX_EINVAL, "need iters >= 1, actions and obs scratch");
+  if (c->n == 0) return JX_OK;
+  HIPCHK(hipSetDevice(c->device));
+  const std::string key = tune_key(c);
+  LaunchCfg hit{};
+  if (cache_lookup(cache_path, key, &hit)) {
+    c->launch = hit;
+    if (chosen) jx_get_launch(c, chosen);
+    return JX_OK;
+  }
+  const size_t total = (size_t)c->L.rdesc;  // the state image
+  const int64_t ob = c->obs_off.back();
+  const int n = c->n;
+  uint8_t* snap = nullptr;
+  uint8_t* io_buf = nullptr;
+  HIPCHK(hipMalloc(&snap, total));
+  if (hipMalloc(&io_buf, (size_t)iters * n * 5) != hipSuccess) {
+    hipFree(snap);
+    return set_error(JX_ENOMEM, "autotune buffers");
+  }
+  float* rew = (float*)io_buf;
+  uint8_t* dn = io_buf + (size_t)iters * n * 4;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  HIPCHK(hipMemcpyAsync(snap, c->ws, total, hipMemcpyDeviceToDevice, c->stream));
+
+  std::vector<LaunchCfg> cands;
+  for (int w : {1, 2, 4, 8})
+    for (int s : {0, 1}) cands.push_back(LaunchCfg{0, w, 1, s});
+  for (int w : {1, 2, 4})
+    for (int g : {2, 4, 8})
+      for (int s : {0, 1}) cands.push_back(LaunchCfg{1, w, g, s});
+  const LaunchCfg keep = c->launch;
+  std::vector<uint8_t> ref_obs(ob), ref_state(total), ref_io((size_t)iters * n * 5);
+  std::vector<uint8_t> cur_obs(ob), cur_state(total), cur_io((size_t)iters * n * 5);
+  float best_ms = 1e30f;
+  LaunchCfg best = cands[0];
+  jx_status result = JX_OK;
+  for (size_t k = 0; k < cands.size() && result == JX_OK; ++k) {
+    c->launch = cands[k];
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 2 && result == JX_OK; ++rep) {
+      hipMemcpyAsync(c->ws, snap, total, hipMemcpyDeviceToDevice, c->stream);
+      hipEventRecord(e0, c->stream);
+      for (int t = 0; t < iters && result == JX_OK; ++t) {
+        DevIo io{};
+        io.act = actions + (int64_t)t * n;
+        io.obs = obs_scratch;
+        io.rew = rew + (int64_t)t * n;
+        io.done = dn + (int64_t)t * n;
+        io.mode = MODE_STEP;
+        io.store_mode = c->launch.store_mode;
+        result = launch_or_fail(c, io, c->stream);
+      }
+      hipEventRecord(e1, c->stream);
+      if (hipStreamSynchronize(c->stream) != hipSuccess) result = set_error(JX_EDEVICE, "autotune run failed");
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, ms);
+    }
+    if (result != JX_OK) break;
+    std::vector<uint8_t>& o = (k == 0) ? ref_obs : cur_obs;
+    std::vector<uint8_t>& s = (k == 0) ? ref_state : cur_state;
+    std::vector<uint8_t>& i2 = (k == 0) ? ref_io : cur_io;
+    hipMemcpy(o.data(), obs_scratch, ob, hipMemcpyDeviceToHost);
+    hipMemcpy(s.data(), c->ws, total, hipMemcpyDeviceToHost);
+    hipMemcpy(i2.data(), io_buf, i2.size(), hipMemcpyDeviceToHost);
+    const bool same = (k == 0) || (o == ref_obs && s == ref_state && i2 == ref_io);
+    if (!same) {
+      result = set_error(JX_EDEVICE, "autotune: candidate mapping changed the results");
+      break;
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = cands[k];
+    }
+  }
+  hipMemcpyAsync(c->ws, snap, total, hipMemcpyDeviceToDevice, c->stream);
+  hipStreamSynchronize(c->stream);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(snap);
+  hipFree(io_buf);
+  if (result != JX_OK) {
+    c->launch = keep;
+    return result;
+  }
+  c->launch = best;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << key << " " << best.form << " " << best.waves_per_group << " " << best.groups_per_cu << " "
+      << best.store_mode << "\n";
+  }
+  if (chosen) jx_get_launch(c, chosen);
+  return JX_OK;
+}

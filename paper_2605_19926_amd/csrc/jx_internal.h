@@ -1,0 +1,124 @@
+// jx_internal.h -- structures shared by the host runtime and the device kernels.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace jx {
+
+constexpr int kMaxSide = 64;     // one map row fits a 64-bit mask; one row per lane in BFS
+constexpr int kMaxW = 128;       // column records per wave in LDS
+constexpr int kMaxH = 128;
+constexpr int kMaxDecor = 2;
+constexpr uint32_t kStateMagic = 0x4A585331u;  // "JXS1"
+
+// Event bits written per env and step.
+constexpr uint32_t EV_BLOCKED_X = 0x01, EV_BLOCKED_Y = 0x02, EV_KEY = 0x04, EV_GOAL = 0x08,
+                   EV_TRUNC = 0x10, EV_INVALID = 0x20, EV_RESET = 0x40;
+// Per-env flag bits.
+constexpr uint32_t FL_KEY = 0x01, FL_DOOR_OPEN = 0x02;
+
+enum Mode : int32_t { MODE_STEP = 0, MODE_RESET = 1, MODE_RENDER = 2 };
+
+// Per-configuration constants, derived on the host from jx_env_cfg.
+struct DevCfg {
+  int32_t side, n_colors, key_door, goal_sprite;
+  int32_t max_decor, obs_h, obs_w, n_actions;
+  int32_t cap, pad0, pad1, pad2;
+  float move, turn, pr2, r_goal;
+  float r_key, tanH, pad3, pad4;
+};
+static_assert(sizeof(DevCfg) == 80, "DevCfg layout");
+
+// First 256 bytes of every workspace.
+struct WsHeader {
+  uint32_t queue;      // persistent form: next work item
+  uint32_t exited;     // persistent form: waves that left the queue
+  uint32_t magic;
+  int32_t n_envs;
+  int64_t state_bytes;
+  int32_t n_cfgs;
+  int32_t pad[57];
+};
+static_assert(sizeof(WsHeader) == 256, "header size");
+
+// Device-resident I/O of a captured rollout: step t uses act + t*n,
+// obs + t*obs_stride, rew + t*n, done + t*n.  Written by a one-thread kernel
+// before each graph replay, so one captured graph serves any buffers.
+struct RolloutDesc {
+  const uint8_t* act;
+  uint8_t* obs;
+  float* rew;
+  uint8_t* done;
+  int64_t obs_stride;
+  int32_t n;
+  int32_t store_mode;
+};
+
+// Device view of one batch of environments (pointers into one workspace).
+struct DevState {
+  float* x;
+  float* y;
+  float* th;
+  uint32_t* t;
+  uint32_t* ep;
+  int32_t* goal;
+  int32_t* door;
+  int32_t* key;
+  int32_t* decor;     // [n][2]
+  uint8_t* flags;
+  uint8_t* events;
+  uint8_t* ndecor;
+  uint32_t* invalid;  // counted invalid actions per env
+  const uint64_t* seed;
+  const int32_t* cfg_idx;
+  const uint32_t* map_off;
+  const int64_t* obs_off;  // [n+1]
+  const int32_t* order;    // persistent work order (costliest first)
+  RolloutDesc* rdesc;      // rollout I/O descriptor
+  const DevCfg* cfgs;
+  const uint8_t* maps;
+  WsHeader* hdr;
+  int32_t n;
+  int32_t pad;
+};
+
+// Per-launch I/O.
+struct DevIo {
+  const uint8_t* act;
+  uint8_t* obs;
+  float* rew;
+  uint8_t* done;
+  void* dbg;          // jx_col_debug[n][dbg_stride]
+  int32_t dbg_stride;
+  int32_t mode;
+  int32_t store_mode;
+  int32_t pad;
+};
+
+// Serving: one work item = (batch descriptor index, env).
+struct ServeItem {
+  int32_t desc;
+  int32_t env;
+};
+
+// Workspace layout: byte offsets of every array.
+struct Layout {
+  int64_t hdr, x, y, th, t, ep, goal, door, key, decor, flags, events, ndecor, invalid, seed,
+      cfg_idx, map_off, obs_off, order, rdesc, cfgs, maps, total;
+};
+
+// Launch entry points implemented in jx_kernels.hip.
+struct LaunchCfg {
+  int32_t form, waves_per_group, groups_per_cu, store_mode;
+};
+// rd != nullptr: the I/O of step t is taken from the device descriptor rd.
+int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t,
+                 const LaunchCfg& lc, int max_side, int n_cu, void* stream);
+int launch_set_desc(RolloutDesc* rd_dev, const RolloutDesc& value, void* stream);
+int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeItem* items_dev,
+                 int n_items, uint32_t* counters_dev, int waves_per_group, int n_groups,
+                 void* stream);
+const char* kernel_error_string(int code);
+
+}  // namespace jx

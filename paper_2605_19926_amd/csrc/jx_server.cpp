@@ -1,0 +1,610 @@
+// jx_server.cpp -- serving form: a request loop that keeps many clients' env
+// batches resident on one device and coalesces their step requests into shared
+// persistent launches (continuous batching).
+//
+// Threads:
+//   caller threads  jx_server_open / submit / wait / close (any number)
+//   scheduler       admits clients (HBM budget, FIFO), packs every ready request
+//                   (its client has no step in flight) into one launch on the
+//                   next free stream: H2D actions, descriptors, work items; the
+//                   serving kernel; D2H frames/rewards/dones; an event
+//   completion      waits for launch events in order, copies each request's
+//                   results out of its client's pinned buffers and completes it
+// A request that arrives while launches are in flight joins the next launch,
+// which can start on another stream before the earlier ones finish.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "jx.h"
+#include "jx_common.h"
+#include "jx_internal.h"
+
+using namespace jx;
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+// First-fit allocator over one device arena with coalescing of free ranges.
+class Arena {
+ public:
+  void init(int64_t bytes) { free_[0] = bytes; }
+  int64_t alloc(int64_t bytes) {
+    bytes = align256(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const int64_t off = it->first;
+        const int64_t rest = it->second - bytes;
+        free_.erase(it);
+        if (rest > 0) free_[off + bytes] = rest;
+        used_ += bytes;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off, int64_t bytes) {
+    bytes = align256(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int64_t used() const { return used_; }
+
+ private:
+  std::map<int64_t, int64_t> free_;
+  int64_t used_ = 0;
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  int client = -1;
+  std::vector<uint8_t> actions;
+  std::vector<uint8_t> obs;
+  std::vector<float> rew;
+  std::vector<uint8_t> done;
+  double t_submit = 0, t_done = 0;
+  int status = 0;  // 0 queued, 1 launched, 2 done, 3 failed
+};
+
+enum ClientState { PENDING, ACTIVE, CLOSED };
+
+struct Client {
+  int id = -1;
+  int n = 0;
+  jx_env_cfg cfg{};
+  std::vector<uint64_t> seeds;
+  ClientState st = PENDING;
+  bool closing = false;
+  bool in_flight = false;
+  // device memory: one arena range holding workspace | obs | act | rew | done
+  int64_t arena_off = -1, bytes = 0;
+  Layout L{};
+  DevState S{};
+  DevIo io{};
+  int64_t obs_bytes = 0;
+  // pinned host staging
+  uint8_t* h_act = nullptr;
+  uint8_t* h_obs = nullptr;
+  float* h_rew = nullptr;
+  uint8_t* h_done = nullptr;
+  std::deque<std::shared_ptr<Request>> queue;
+};
+
+struct Launch {
+  int stream = 0;
+  hipEvent_t ev = nullptr;
+  std::vector<std::shared_ptr<Request>> reqs;
+};
+
+struct StreamSlot {
+  hipStream_t s = nullptr;
+  bool busy = false;
+  DevState* d_states = nullptr;
+  DevIo* d_ios = nullptr;
+  ServeItem* d_items = nullptr;
+  uint32_t* d_counters = nullptr;
+  DevState* h_states = nullptr;
+  DevIo* h_ios = nullptr;
+  ServeItem* h_items = nullptr;
+  hipEvent_t ev = nullptr;
+};
+
+constexpr int kMaxClientsPerLaunch = 1024;
+constexpr int kMaxItemsPerLaunch = 1 << 18;
+
+}  // namespace
+
+struct jx_server {
+  int device = 0;
+  int mode = JX_SERVE_COALESCE;
+  int max_batch_envs = 0;
+  int n_cu = 1;
+  int64_t budget = 0;
+  uint8_t* arena_base = nullptr;
+  Arena arena;
+  std::vector<StreamSlot> streams;
+  hipStream_t admin = nullptr;
+  int next_stream = 0;
+
+  std::mutex mu;
+  std::condition_variable cv_sched;   // scheduler: new work / stream freed / stop
+  std::condition_variable cv_done;    // waiters: a request completed
+  std::condition_variable cv_comp;    // completion thread: a launch was issued
+  std::map<int, std::unique_ptr<Client>> clients;
+  std::deque<int> pending;            // admission FIFO
+  std::map<uint64_t, std::shared_ptr<Request>> requests;
+  std::deque<Launch> inflight;
+  uint64_t next_ticket = 1;
+  int next_client = 0;
+  bool stop = false;
+  std::string fatal;
+  jx_server_stats stats{};
+  std::thread sched, comp;
+};
+
+namespace {
+
+// Device bytes of a client: workspace, frames, actions, rewards, dones.
+int64_t client_bytes(int n, const jx_env_cfg& cfg, Layout* L, int64_t* obs_bytes) {
+  *L = make_layout(n, 1, (int64_t)n * map_bytes_of(cfg.side));
+  *obs_bytes = (int64_t)n * cfg.obs_h * cfg.obs_w * 3;
+  return align256(L->total) + align256(*obs_bytes) + align256(n) + align256(4 * (int64_t)n) +
+         align256(n);
+}
+
+// Uploads a freshly generated image and runs the episode-0 reset.  Called
+// without the server lock; the client's arena range is already reserved.
+jx_status activate(jx_server* s, Client* c) {
+  std::vector<uint8_t> img;
+  Layout L;
+  std::vector<int64_t> oo;
+  std::vector<int32_t> idx;
+  jx_status st = build_image(c->n, c->seeds.data(), &c->cfg, 1, nullptr, &img, &L, &oo, &idx);
+  if (st) return st;
+  uint8_t* base = s->arena_base + c->arena_off;
+  uint8_t* ws = base;
+  uint8_t* obs = ws + align256(L.total);
+  uint8_t* act = obs + align256(c->obs_bytes);
+  uint8_t* rew = act + align256(c->n);
+  uint8_t* dn = rew + align256(4 * (int64_t)c->n);
+  c->L = L;
+  c->S = bind_state(ws, L, c->n);
+  c->io = DevIo{};
+  c->io.act = act;
+  c->io.obs = obs;
+  c->io.rew = (float*)rew;
+  c->io.done = dn;
+  c->io.mode = MODE_STEP;
+  if (hipHostMalloc((void**)&c->h_act, std::max(c->n, 1)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_obs, std::max<int64_t>(c->obs_bytes, 1)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_rew, 4 * std::max(c->n, 1)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_done, std::max(c->n, 1)) != hipSuccess)
+    return set_error(JX_ENOMEM, "pinned host buffers");
+  if (hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, s->admin) != hipSuccess)
+    return set_error(JX_EDEVICE, "client upload failed");
+  DevIo io{};
+  io.mode = MODE_RESET;
+  int rc = launch_batch(c->S, io, nullptr, 0, LaunchCfg{0, 1, 1, 0}, c->cfg.side, s->n_cu, s->admin);
+  if (rc) return set_error(JX_EDEVICE, std::string("client reset: ") + kernel_error_string(rc));
+  if (hipStreamSynchronize(s->admin) != hipSuccess) return set_error(JX_EDEVICE, "client reset sync failed");
+  return JX_OK;
+}
+
+void free_client_memory(jx_server* s, Client* c) {
+  if (c->arena_off >= 0) s->arena.release(c->arena_off, c->bytes);
+  c->arena_off = -1;
+  if (c->h_act) hipHostFree(c->h_act);
+  if (c->h_obs) hipHostFree(c->h_obs);
+  if (c->h_rew) hipHostFree(c->h_rew);
+  if (c->h_done) hipHostFree(c->h_done);
+  c->h_act = c->h_obs = c->h_done = nullptr;
+  c->h_rew = nullptr;
+}
+
+// Admits pending clients in FIFO order while the budget allows (lock held on
+// entry and exit; released around the device work).
+void admit_pending(jx_server* s, std::unique_lock<std::mutex>& lk) {
+  while (!s->pending.empty()) {
+    Client* c = s->clients[s->pending.front()].get();
+    const int64_t off = s->arena.alloc(c->bytes);
+    if (off < 0) return;
+    c->arena_off = off;
+    s->pending.pop_front();
+    lk.unlock();
+    jx_status st = activate(s, c);
+    lk.lock();
+    if (st != JX_OK) {
+      s->fatal = "admission failed: " + std::string(jx_last_error());
+      c->st = CLOSED;
+      for (auto& r : c->queue) r->status = 3;
+      c->queue.clear();
+      free_client_memory(s, c);
+      s->cv_done.notify_all();
+      continue;
+    }
+    c->st = ACTIVE;
+    s->stats.clients_pending -= 1;
+    s->stats.clients_active += 1;
+  }
+}
+
+void reap_closed(jx_server* s) {
+  bool freed = false;
+  for (auto& kv : s->clients) {
+    Client* c = kv.second.get();
+    if (c->closing && c->st == ACTIVE && !c->in_flight && c->queue.empty()) {
+      free_client_memory(s, c);
+      c->st = CLOSED;
+      s->stats.clients_active -= 1;
+      freed = true;
+    }
+  }
+  if (freed) {
+    for (auto it = s->clients.begin(); it != s->clients.end();) {
+      if (it->second->st == CLOSED && it->second->queue.empty()) it = s->clients.erase(it);
+      else ++it;
+    }
+  }
+}
+
+// Builds and issues one launch on stream slot k from the ready clients.
+void issue(jx_server* s, int k, std::vector<Client*>& batch) {
+  StreamSlot& ss = s->streams[k];
+  Launch L;
+  L.stream = k;
+  L.ev = ss.ev;
+  int n_items = 0;
+  for (size_t d = 0; d < batch.size(); ++d) {
+    Client* c = batch[d];
+    std::shared_ptr<Request> r = c->queue.front();
+    c->queue.pop_front();
+    c->in_flight = true;
+    r->status = 1;
+    L.reqs.push_back(r);
+    std::memcpy(c->h_act, r->actions.data(), c->n);
+    ss.h_states[d] = c->S;
+    ss.h_ios[d] = c->io;
+    for (int e = 0; e < c->n; ++e) ss.h_items[n_items++] = ServeItem{(int32_t)d, e};
+  }
+  hipStream_t st = ss.s;
+  bool ok = true;
+  for (Client* c : batch)
+    ok = ok && hipMemcpyAsync((void*)c->io.act, c->h_act, c->n, hipMemcpyHostToDevice, st) == hipSuccess;
+  if (s->mode == JX_SERVE_PLAIN) {
+    Client* c = batch[0];
+    ok = ok && launch_batch(c->S, c->io, nullptr, 0, LaunchCfg{0, 1, 1, 0}, c->cfg.side, s->n_cu, st) == 0;
+  } else {
+    ok = ok && hipMemcpyAsync(ss.d_states, ss.h_states, sizeof(DevState) * batch.size(),
+                              hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(ss.d_ios, ss.h_ios, sizeof(DevIo) * batch.size(), hipMemcpyHostToDevice,
+                              st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(ss.d_items, ss.h_items, sizeof(ServeItem) * n_items, hipMemcpyHostToDevice,
+                              st) == hipSuccess;
+    const int wpb = 2;
+    int groups = std::min((n_items + wpb - 1) / wpb, s->n_cu * 4);
+    groups = std::max(groups, 1);
+    ok = ok && launch_serve(ss.d_states, ss.d_ios, ss.d_items, n_items, ss.d_counters, wpb, groups, st) == 0;
+  }
+  for (Client* c : batch) {
+    ok = ok && hipMemcpyAsync(c->h_obs, c->io.obs, c->obs_bytes, hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(c->h_rew, c->io.rew, 4 * (size_t)c->n, hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(c->h_done, c->io.done, c->n, hipMemcpyDeviceToHost, st) == hipSuccess;
+  }
+  ok = ok && hipEventRecord(ss.ev, st) == hipSuccess;
+  if (!ok) {
+    s->fatal = "launch failed";
+    for (auto& r : L.reqs) r->status = 3;
+    for (Client* c : batch) c->in_flight = false;
+    s->cv_done.notify_all();
+    return;
+  }
+  ss.busy = true;
+  s->stats.launches += 1;
+  s->stats.env_steps += n_items;
+  s->inflight.push_back(std::move(L));
+  s->cv_comp.notify_one();
+}
+
+void scheduler_main(jx_server* s) {
+  hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    reap_closed(s);
+    admit_pending(s, lk);
+    // ready clients, oldest request first
+    std::vector<Client*> ready;
+    for (auto& kv : s->clients) {
+      Client* c = kv.second.get();
+      if (c->st == ACTIVE && !c->in_flight && !c->queue.empty()) ready.push_back(c);
+    }
+    int k = -1;
+    for (int j = 0; j < (int)s->streams.size(); ++j) {
+      int cand = (s->next_stream + j) % (int)s->streams.size();
+      if (!s->streams[cand].busy) {
+        k = cand;
+        break;
+      }
+    }
+    if (ready.empty() || k < 0) {
+      s->cv_sched.wait(lk);
+      continue;
+    }
+    std::sort(ready.begin(), ready.end(), [](Client* a, Client* b) {
+      return a->queue.front()->ticket < b->queue.front()->ticket;
+    });
+    std::vector<Client*> batch;
+    int envs = 0;
+    for (Client* c : ready) {
+      if (s->mode == JX_SERVE_PLAIN && !batch.empty()) break;
+      if (!batch.empty() && s->max_batch_envs > 0 && envs + c->n > s->max_batch_envs) continue;
+      if ((int)batch.size() >= kMaxClientsPerLaunch || envs + c->n > kMaxItemsPerLaunch) break;
+      batch.push_back(c);
+      envs += c->n;
+    }
+    s->next_stream = (k + 1) % (int)s->streams.size();
+    issue(s, k, batch);
+  }
+}
+
+void completion_main(jx_server* s) {
+  hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    while (s->inflight.empty() && !s->stop) s->cv_comp.wait(lk);
+    if (s->inflight.empty() && s->stop) return;
+    hipEvent_t ev = s->inflight.front().ev;
+    lk.unlock();
+    hipError_t e = hipEventSynchronize(ev);
+    const double t = now_s();
+    lk.lock();
+    Launch L = std::move(s->inflight.front());
+    s->inflight.pop_front();
+    for (auto& r : L.reqs) {
+      auto it = s->clients.find(r->client);
+      Client* c = it == s->clients.end() ? nullptr : it->second.get();
+      if (e == hipSuccess && c) {
+        r->obs.assign(c->h_obs, c->h_obs + c->obs_bytes);
+        r->rew.assign(c->h_rew, c->h_rew + c->n);
+        r->done.assign(c->h_done, c->h_done + c->n);
+        r->status = 2;
+      } else {
+        r->status = 3;
+      }
+      r->t_done = t;
+      if (c) c->in_flight = false;
+      s->stats.requests += 1;
+    }
+    if (e != hipSuccess) s->fatal = std::string("device error: ") + hipGetErrorString(e);
+    s->streams[L.stream].busy = false;
+    s->cv_done.notify_all();
+    s->cv_sched.notify_one();
+  }
+}
+
+}  // namespace
+
+#define SRV_CHK(expr, msg)                          \
+  do {                                              \
+    if ((expr) != hipSuccess) {                     \
+      jx_server_destroy(s);                         \
+      return set_error(JX_EDEVICE, msg);            \
+    }                                               \
+  } while (0)
+
+extern "C" {
+
+jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_bytes, int32_t n_streams,
+                           int32_t mode, int32_t max_batch_envs) {
+  if (!out) return set_error(JX_EINVAL, "out is null");
+  *out = nullptr;
+  if (n_streams < 1 || n_streams > 8) return set_error(JX_EINVAL, "n_streams must be in 1..8");
+  if (mode != JX_SERVE_COALESCE && mode != JX_SERVE_PLAIN) return set_error(JX_EINVAL, "bad mode");
+  if (hbm_budget_bytes < 4096) return set_error(JX_EINVAL, "budget too small");
+  if (max_batch_envs < 0) return set_error(JX_EINVAL, "max_batch_envs < 0");
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev)
+    return set_error(JX_EINVAL, "bad device index");
+  hipSetDevice(device);
+  jx_server* s = new jx_server();
+  s->device = device;
+  s->mode = mode;
+  s->max_batch_envs = max_batch_envs;
+  s->budget = (int64_t)hbm_budget_bytes;
+  hipDeviceProp_t p;
+  SRV_CHK(hipGetDeviceProperties(&p, device), "device properties");
+  s->n_cu = std::max(1, p.multiProcessorCount);
+  SRV_CHK(hipMalloc((void**)&s->arena_base, hbm_budget_bytes), "HBM budget allocation failed");
+  s->arena.init((int64_t)hbm_budget_bytes);
+  SRV_CHK(hipStreamCreateWithFlags(&s->admin, hipStreamNonBlocking), "stream");
+  const int ns = (mode == JX_SERVE_PLAIN) ? 1 : n_streams;
+  s->streams.resize(ns);
+  for (auto& ss : s->streams) {
+    SRV_CHK(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking), "stream");
+    SRV_CHK(hipEventCreateWithFlags(&ss.ev, hipEventDisableTiming), "event");
+    SRV_CHK(hipMalloc((void**)&ss.d_states, sizeof(DevState) * kMaxClientsPerLaunch), "alloc");
+    SRV_CHK(hipMalloc((void**)&ss.d_ios, sizeof(DevIo) * kMaxClientsPerLaunch), "alloc");
+    SRV_CHK(hipMalloc((void**)&ss.d_items, sizeof(ServeItem) * kMaxItemsPerLaunch), "alloc");
+    SRV_CHK(hipMalloc((void**)&ss.d_counters, 256), "alloc");
+    SRV_CHK(hipMemset(ss.d_counters, 0, 256), "memset");
+    SRV_CHK(hipHostMalloc((void**)&ss.h_states, sizeof(DevState) * kMaxClientsPerLaunch), "pinned");
+    SRV_CHK(hipHostMalloc((void**)&ss.h_ios, sizeof(DevIo) * kMaxClientsPerLaunch), "pinned");
+    SRV_CHK(hipHostMalloc((void**)&ss.h_items, sizeof(ServeItem) * kMaxItemsPerLaunch), "pinned");
+  }
+  SRV_CHK(hipDeviceSynchronize(), "sync");
+  s->sched = std::thread(scheduler_main, s);
+  s->comp = std::thread(completion_main, s);
+  *out = s;
+  return JX_OK;
+}
+
+void jx_server_destroy(jx_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv_sched.notify_all();
+  s->cv_comp.notify_all();
+  if (s->sched.joinable()) s->sched.join();
+  if (s->comp.joinable()) s->comp.join();
+  hipSetDevice(s->device);
+  hipDeviceSynchronize();
+  for (auto& kv : s->clients) free_client_memory(s, kv.second.get());
+  for (auto& ss : s->streams) {
+    if (ss.s) hipStreamDestroy(ss.s);
+    if (ss.ev) hipEventDestroy(ss.ev);
+    if (ss.d_states) hipFree(ss.d_states);
+    if (ss.d_ios) hipFree(ss.d_ios);
+    if (ss.d_items) hipFree(ss.d_items);
+    if (ss.d_counters) hipFree(ss.d_counters);
+    if (ss.h_states) hipHostFree(ss.h_states);
+    if (ss.h_ios) hipHostFree(ss.h_ios);
+    if (ss.h_items) hipHostFree(ss.h_items);
+  }
+  if (s->admin) hipStreamDestroy(s->admin);
+  if (s->arena_base) hipFree(s->arena_base);
+  delete s;
+}
+
+jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, const jx_env_cfg* cfg,
+                         int32_t* client) {
+  if (!s || !seeds || !cfg || !client) return set_error(JX_EINVAL, "null argument");
+  if (n_envs < 1 || n_envs > kMaxItemsPerLaunch) return set_error(JX_EINVAL, "n_envs out of range");
+  std::string why;
+  if (!validate_cfg(*cfg, &why)) return set_error(JX_EINVAL, why);
+  auto c = std::make_unique<Client>();
+  c->n = n_envs;
+  c->cfg = *cfg;
+  c->seeds.assign(seeds, seeds + n_envs);
+  c->bytes = client_bytes(n_envs, *cfg, &c->L, &c->obs_bytes);
+  if (c->bytes > s->budget) return set_error(JX_ENOMEM, "client exceeds the HBM budget on its own");
+  std::unique_lock<std::mutex> lk(s->mu);
+  const int id = s->next_client++;
+  c->id = id;
+  Client* cp = c.get();
+  s->clients[id] = std::move(c);
+  *client = id;
+  const bool fifo_empty = s->pending.empty();
+  const int64_t off = fifo_empty ? s->arena.alloc(cp->bytes) : -1;
+  if (off < 0) {
+    s->pending.push_back(id);
+    s->stats.clients_pending += 1;
+    s->stats.admission_waits += 1;
+    return JX_EBUSY;
+  }
+  cp->arena_off = off;
+  lk.unlock();
+  jx_status st = activate(s, cp);
+  lk.lock();
+  if (st != JX_OK) {
+    free_client_memory(s, cp);
+    s->clients.erase(id);
+    return st;
+  }
+  cp->st = ACTIVE;
+  s->stats.clients_active += 1;
+  s->cv_sched.notify_one();
+  return JX_OK;
+}
+
+jx_status jx_server_submit(jx_server* s, int32_t client, const uint8_t* actions, uint64_t* ticket) {
+  if (!s || !actions || !ticket) return set_error(JX_EINVAL, "null argument");
+  auto r = std::make_shared<Request>();
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (!s->fatal.empty()) return set_error(JX_EDEVICE, s->fatal);
+  auto it = s->clients.find(client);
+  if (it == s->clients.end() || it->second->closing || it->second->st == CLOSED)
+    return set_error(JX_EINVAL, "unknown or closed client");
+  Client* c = it->second.get();
+  r->ticket = s->next_ticket++;
+  r->client = client;
+  r->actions.assign(actions, actions + c->n);
+  r->t_submit = now_s();
+  c->queue.push_back(r);
+  s->requests[r->ticket] = r;
+  *ticket = r->ticket;
+  s->cv_sched.notify_one();
+  return JX_OK;
+}
+
+jx_status jx_server_wait(jx_server* s, uint64_t ticket, double timeout_s, uint8_t* obs, float* rew,
+                         uint8_t* done, double* latency) {
+  if (!s) return set_error(JX_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return set_error(JX_EINVAL, "unknown ticket");
+  std::shared_ptr<Request> r = it->second;
+  auto finished = [&] { return r->status >= 2; };
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, finished);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), finished)) {
+    return JX_EBUSY;
+  }
+  s->requests.erase(ticket);
+  if (r->status == 3) return set_error(JX_EDEVICE, s->fatal.empty() ? "request failed" : s->fatal);
+  if (obs) std::memcpy(obs, r->obs.data(), r->obs.size());
+  if (rew) std::memcpy(rew, r->rew.data(), 4 * r->rew.size());
+  if (done) std::memcpy(done, r->done.data(), r->done.size());
+  if (latency) *latency = r->t_done - r->t_submit;
+  return JX_OK;
+}
+
+jx_status jx_server_close(jx_server* s, int32_t client) {
+  if (!s) return set_error(JX_EINVAL, "null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->clients.find(client);
+  if (it == s->clients.end()) return set_error(JX_EINVAL, "unknown client");
+  Client* c = it->second.get();
+  if (c->st == PENDING) {
+    // never admitted: drop it from the FIFO and fail its queued requests
+    s->pending.erase(std::remove(s->pending.begin(), s->pending.end(), client), s->pending.end());
+    for (auto& r : c->queue) r->status = 3;
+    c->queue.clear();
+    c->st = CLOSED;
+    s->stats.clients_pending -= 1;
+    s->clients.erase(it);
+    s->cv_done.notify_all();
+  } else {
+    c->closing = true;
+  }
+  s->cv_sched.notify_one();
+  return JX_OK;
+}
+
+jx_status jx_server_get_stats(jx_server* s, jx_server_stats* out) {
+  if (!s || !out) return set_error(JX_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  *out = s->stats;
+  out->bytes_in_use = s->arena.used();
+  return JX_OK;
+}
+
+}  // extern "C"

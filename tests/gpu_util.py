@@ -1,0 +1,203 @@
+"""Helpers shared by the GPU parity tests: synthetic states, oracle comparisons.
+
+Oracle inputs come only from the seeded generators (workloads) and the oracle
+itself; values produced by the HIP path are only ever compared, never fed to
+the oracle.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle as orc
+import workloads as W
+
+TWO_PI = 2 * math.pi
+T_REL = 1e-4          # perpendicular distance, relative
+FLAG_LIMIT = 1e-3     # flagged columns must stay below 0.1 %
+
+
+def env_of(cfgs, seeds, cfg_index=None, obs=True):
+    import torch
+    from paper_2605_19926_amd import jx
+    e = jx.Env(seeds, cfgs, cfg_index)
+    e.obs0 = None
+    if obs:
+        # size the first frame buffer after the reset computes offsets
+        e.reset()
+        e.obs0 = torch.empty(e.obs_bytes, dtype=torch.uint8, device=e.dev)
+        e.reset(e.obs0)
+    else:
+        e.reset()
+    return e
+
+
+def oracle_maze(cfg: dict, seed: int) -> np.ndarray:
+    return orc.maze(int(seed), cfg["side"], cfg["loop_frac"])
+
+
+def ulp_close(a32, b64, k=2):
+    a32 = np.float32(a32)
+    return abs(float(a32) - float(b64)) <= k * float(np.spacing(np.float32(abs(b64)) + np.float32(0)))
+
+
+def angle_close(a, b, tol=1e-6):
+    d = (float(a) - float(b) + math.pi) % TWO_PI - math.pi
+    return abs(d) <= tol
+
+
+def synth_state(rng, cfg: dict, seed: int, grid: np.ndarray) -> dict:
+    """A reachable-looking state: structural fields from an oracle episode reset
+    of a random episode, a random float32 pose in a free tile, random time and
+    key status."""
+    oc = orc.make_cfg(cfg)
+    ep = int(rng.integers(0, 60))
+    st = orc.reset(grid, oc, int(seed), ep).as_dict()
+    key_taken = int(rng.integers(0, 2)) if st["key"] >= 0 else 0
+    N = cfg["side"]
+    free = np.argwhere(grid == 0)[:, ::-1]                  # (x, y)
+    if st["door"] >= 0 and not key_taken:
+        free = free[(free[:, 1] * N + free[:, 0]) != st["door"]]
+    x, y, th = W.random_poses(rng, free, 1)
+    st.update(x=float(x[0]), y=float(y[0]), theta=float(th[0]),
+              t=int(rng.integers(0, cfg["episode_cap"])), key_taken=key_taken,
+              door_open=key_taken)
+    return st
+
+
+def gpu_fields(states: list[dict]) -> dict:
+    n = len(states)
+    f = {"x": np.array([s["x"] for s in states], np.float32),
+         "y": np.array([s["y"] for s in states], np.float32),
+         "theta": np.array([s["theta"] for s in states], np.float32),
+         "t": np.array([s["t"] for s in states], np.uint32),
+         "episode": np.array([s["episode"] for s in states], np.uint32),
+         "goal": np.array([s["goal"] for s in states], np.int32),
+         "door": np.array([s["door"] for s in states], np.int32),
+         "key": np.array([s["key"] for s in states], np.int32),
+         "decor": np.array([list(s["decor"])[:2] for s in states], np.int32).reshape(-1),
+         "flags": np.array([s["key_taken"] | (s["door_open"] << 1) for s in states], np.uint8),
+         "n_decor": np.array([s["n_decor"] for s in states], np.uint8)}
+    assert f["x"].shape == (n,)
+    return f
+
+
+def gpu_state_dict(S: dict, i: int) -> dict:
+    return {"x": float(S["x"][i]), "y": float(S["y"][i]), "theta": float(S["theta"][i]),
+            "t": int(S["t"][i]), "episode": int(S["episode"][i]), "goal": int(S["goal"][i]),
+            "door": int(S["door"][i]), "key": int(S["key"][i]),
+            "key_taken": int(S["flags"][i] & 1), "door_open": int((S["flags"][i] >> 1) & 1),
+            "n_decor": int(S["n_decor"][i]), "decor": [int(S["decor"][2 * i]), int(S["decor"][2 * i + 1])]}
+
+
+EXACT_KEYS = ("t", "episode", "goal", "door", "key", "key_taken", "door_open", "n_decor")
+
+
+def compare_reset_state(g: dict, o: dict) -> list[str]:
+    """Episode-start states are exact on both sides (integer draws, one float32
+    multiply for the heading)."""
+    errs = []
+    for k in ("x", "y", "theta"):
+        if float(np.float32(g[k])) != o[k]:
+            errs.append(f"{k}: gpu {g[k]!r} oracle {o[k]!r}")
+    for k in EXACT_KEYS:
+        if g[k] != o[k]:
+            errs.append(f"{k}: gpu {g[k]} oracle {o[k]}")
+    nd = o["n_decor"]
+    if list(g["decor"])[:nd] != list(o["decor"])[:nd]:
+        errs.append(f"decor: gpu {g['decor']} oracle {o['decor']}")
+    return errs
+
+
+class FrameStats:
+    def __init__(self):
+        self.cols = 0
+        self.flagged = 0
+        self.f1 = 0
+        self.mismatch = []
+
+    def frac_flagged(self):
+        return self.flagged / max(1, self.cols)
+
+    def summary(self):
+        return (f"columns {self.cols}, flagged {self.flagged} ({100 * self.frac_flagged():.4f}%),"
+                f" F1 {self.f1}, unflagged mismatches {len(self.mismatch)}")
+
+
+def compare_frame(stats: FrameStats, g_obs: np.ndarray, o_obs: np.ndarray, cols: dict,
+                  g_dbg=None, tag=""):
+    """Unflagged columns: every pixel bit-exact; with debug records also hit and
+    side exact and t* within 1e-4 relative.  Flagged F1 columns: the GPU's (hit,
+    side) must equal one of the two branches."""
+    W_ = o_obs.shape[1]
+    fl = cols["flags"]
+    stats.cols += W_
+    stats.flagged += int((fl != 0).sum())
+    stats.f1 += int(((fl & orc.CF_DDA) != 0).sum())
+    diff_cols = np.nonzero((g_obs != o_obs).any(axis=(0, 2)))[0]
+    for c in diff_cols:
+        if fl[c] == 0:
+            stats.mismatch.append(f"{tag} pixel column {c}")
+    if g_dbg is not None:
+        for c in range(W_):
+            gh, gs, gt = int(g_dbg["hit"][c]), int(g_dbg["side"][c]), float(g_dbg["t"][c])
+            if fl[c] == 0:
+                if gh != cols["hit"][c] or gs != cols["side"][c]:
+                    stats.mismatch.append(f"{tag} col {c}: hit/side gpu {(gh, gs)} oracle "
+                                          f"{(int(cols['hit'][c]), int(cols['side'][c]))}")
+                elif abs(gt - cols["t"][c]) > T_REL * cols["t"][c]:
+                    stats.mismatch.append(f"{tag} col {c}: t gpu {gt} oracle {cols['t'][c]}")
+            elif (fl[c] & orc.CF_DDA) and not (fl[c] & orc.CF_MULTI):
+                ok = (gh == cols["hit"][c] and gs == cols["side"][c]) or \
+                     (gh == cols["alt_hit"][c] and gs == cols["alt_side"][c])
+                if not ok:
+                    stats.mismatch.append(f"{tag} col {c}: F1 branch gpu {(gh, gs)} not in "
+                                          f"{(int(cols['hit'][c]), int(cols['side'][c]))} / "
+                                          f"{(int(cols['alt_hit'][c]), int(cols['alt_side'][c]))}")
+
+
+def frame_of(obs_np: np.ndarray, offsets: np.ndarray, i: int, H: int, W_: int) -> np.ndarray:
+    return obs_np[offsets[i]:offsets[i] + H * W_ * 3].reshape(H, W_, 3)
+
+
+def round32(o: dict) -> dict:
+    """The oracle's state in the float32 storage format both sides keep."""
+    r = dict(o)
+    for k in ("x", "y", "theta"):
+        r[k] = float(np.float32(o[k]))
+    return r
+
+
+def same_pose(g: dict, o32: dict) -> bool:
+    return all(float(np.float32(g[k])) == o32[k] for k in ("x", "y", "theta"))
+
+
+def compare_step(gs_before: dict, cfg: dict, seed: int, grid: np.ndarray, action: int,
+                 g_after: dict, g_rew: float, g_done: int, g_ev: int):
+    """One transition from a shared input state.  Returns (skipped, errors,
+    oracle next state dict).  Steps the oracle flags (S1-S3) are skipped."""
+    oc = orc.make_cfg(cfg)
+    st = orc.state_from(gs_before)
+    nxt, r, d, ev, sf = orc.step(grid, oc, int(seed), st, int(action))
+    o = nxt.as_dict()
+    if sf:
+        return True, [], o
+    errs = []
+    if int(g_done) != d:
+        errs.append(f"done gpu {g_done} oracle {d}")
+    if float(g_rew) != r:
+        errs.append(f"reward gpu {g_rew} oracle {r}")
+    if int(g_ev) != ev:
+        errs.append(f"events gpu {g_ev:#x} oracle {ev:#x}")
+    if d:
+        errs += compare_reset_state(g_after, o)
+    else:
+        if not ulp_close(g_after["x"], o["x"]) or not ulp_close(g_after["y"], o["y"]):
+            errs.append(f"pos gpu {(g_after['x'], g_after['y'])} oracle {(o['x'], o['y'])}")
+        if not angle_close(g_after["theta"], o["theta"]):
+            errs.append(f"theta gpu {g_after['theta']} oracle {o['theta']}")
+        for k in EXACT_KEYS:
+            if g_after[k] != o[k]:
+                errs.append(f"{k}: gpu {g_after[k]} oracle {o[k]}")
+    return False, errs, o

@@ -1,0 +1,294 @@
+"""GPU: the batching and serving forms, checkpoint/resume and edge cases.
+
+Every mapping of envs to waves computes each env with the same per-env code,
+so the forms must agree with the plain launch on every output byte.  The
+mixed-shape batch is also checked against the oracle."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import workloads as W
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(env, acts_d, T, mode, torch):
+    """T steps in the given launch mode; returns (obs[T], rew[T], done[T], state image)."""
+    n, ob = env.n, env.obs_bytes
+    obs = torch.zeros(T * ob, dtype=torch.uint8, device=env.dev)
+    rew = torch.zeros(T * n, dtype=torch.float32, device=env.dev)
+    done = torch.zeros(T * n, dtype=torch.uint8, device=env.dev)
+    if mode == "eager":
+        for t in range(T):
+            env.step(acts_d[t], obs[t * ob:(t + 1) * ob], rew[t * n:(t + 1) * n], done[t * n:(t + 1) * n])
+    elif mode == "rollout_eager":
+        env.rollout(acts_d, obs, rew, done, T, obs_stride=ob, graph=False)
+    else:
+        env.rollout(acts_d, obs, rew, done, T, obs_stride=ob, graph=True)
+    torch.cuda.synchronize()
+    return obs.cpu().numpy(), rew.cpu().numpy(), done.cpu().numpy(), env.get_state_bytes()
+
+
+def _forms_equal(cfgs, seeds, cfg_index, T, launches):
+    import torch
+    env = U.env_of(cfgs, seeds, cfg_index, obs=False)
+    n_act = max(c["n_actions"] for c in (cfgs if isinstance(cfgs, list) else [cfgs]))
+    acts = W.actions(9, T, len(seeds), n_act)
+    acts_d = torch.from_numpy(acts).to(env.dev)
+    snap = env.get_state_bytes()
+    ref = None
+    for mode, launch in launches:
+        env.set_state_bytes(snap)
+        env.set_launch(**launch)
+        out = _run(env, acts_d, T, mode, torch)
+        if ref is None:
+            ref = out
+            continue
+        for k, name in enumerate(("obs", "reward", "done", "state")):
+            assert np.array_equal(out[k], ref[k]), f"{mode} {launch}: {name} differs"
+    env.close()
+    return ref
+
+
+PLAIN1 = dict(form=0, waves_per_group=1, groups_per_cu=1, store_mode=0)
+
+
+def test_graph_eager_persistent_identical():
+    cfg = W.SCALE["cfg"]
+    seeds = W.seeds(W.SCALE["number"], 1024)
+    launches = [("eager", PLAIN1),
+                ("rollout_eager", dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=1)),
+                ("graph", dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0)),
+                ("graph", dict(form=1, waves_per_group=2, groups_per_cu=2, store_mode=0)),
+                ("graph", dict(form=1, waves_per_group=4, groups_per_cu=8, store_mode=1)),
+                ("eager", dict(form=1, waves_per_group=1, groups_per_cu=1, store_mode=0))]
+    _forms_equal(cfg, seeds, None, 40, launches)
+
+
+def test_graph_replays_agree_with_eager():
+    """A captured rollout replayed several times (with eager work and syncs in
+    between) equals the same steps launched one by one."""
+    import torch
+    cfg = W.TINY["cfg"]
+    seeds = W.seeds(1, 64)
+    T, R = 16, 4
+    acts = W.actions(3, T * R, 64, 4)
+    env = U.env_of(cfg, seeds, obs=False)
+    snap = env.get_state_bytes()
+    acts_d = torch.from_numpy(acts).to(env.dev)
+    e = [_run(env, acts_d[r * T:(r + 1) * T], T, "eager", torch) for r in range(R)]
+    env.set_state_bytes(snap)
+    for r in range(R):
+        g = _run(env, acts_d[r * T:(r + 1) * T], T, "graph", torch)
+        for k in range(4):
+            assert np.array_equal(g[k], e[r][k]), f"replay {r} field {k}"
+        env.render(torch.zeros(env.obs_bytes, dtype=torch.uint8, device=env.dev))
+        torch.cuda.synchronize()
+    env.close()
+
+
+def test_mixed_shapes_batch_identical_and_oracle():
+    import torch
+    n = 2048
+    cfgs, idx = W.batch_cfgs(n)
+    seeds = W.seeds(W.BATCH["number"], n)
+    launches = [("eager", PLAIN1),
+                ("graph", dict(form=1, waves_per_group=2, groups_per_cu=4, store_mode=0)),
+                ("graph", dict(form=1, waves_per_group=1, groups_per_cu=8, store_mode=1))]
+    _forms_equal(cfgs, seeds, idx, 12, launches)
+    # oracle parity of the mixed batch from shared states (render + one step)
+    env = U.env_of(cfgs, seeds, idx, obs=False)
+    env.set_launch(form=1, waves_per_group=2, groups_per_cu=4, store_mode=0)
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(n, 96, replace=False))
+    S0 = env.get_state()
+    states = [U.gpu_state_dict(S0, i) for i in range(n)]
+    grids = {}
+    for i in pick:
+        c = cfgs[idx[i]]
+        grids[int(i)] = U.oracle_maze(c, seeds[i])
+        states[int(i)] = U.synth_state(rng, c, seeds[i], grids[int(i)])
+    env.set_state(U.gpu_fields(states))
+    obs = torch.empty(env.obs_bytes, dtype=torch.uint8, device=env.dev)
+    env.render(obs)
+    acts = rng.integers(0, 6, size=n).astype(np.uint8)
+    obs2 = torch.empty(env.obs_bytes, dtype=torch.uint8, device=env.dev)
+    env.step(torch.from_numpy(acts).to(env.dev), obs2)
+    torch.cuda.synchronize()
+    o1, o2 = obs.cpu().numpy(), obs2.cpu().numpy()
+    S = env.get_state()
+    rew, done = env.reward.cpu().numpy(), env.done.cpu().numpy()
+    stats = U.FrameStats()
+    for i in pick:
+        i = int(i)
+        c = cfgs[idx[i]]
+        oo, cols = orc.render(grids[i], orc.make_cfg(c), orc.state_from(states[i]))
+        U.compare_frame(stats, U.frame_of(o1, env.obs_offsets, i, c["obs_h"], c["obs_w"]), oo, cols,
+                        tag=f"render env {i}")
+        skip, errs, o = U.compare_step(states[i], c, seeds[i], grids[i], acts[i],
+                                       U.gpu_state_dict(S, i), rew[i], done[i], S["events"][i])
+        assert skip or not errs, (i, errs)
+        if not skip and U.same_pose(U.gpu_state_dict(S, i), U.round32(o)):
+            oo, cols = orc.render(grids[i], orc.make_cfg(c), orc.state_from(U.round32(o)))
+            U.compare_frame(stats, U.frame_of(o2, env.obs_offsets, i, c["obs_h"], c["obs_w"]), oo,
+                            cols, tag=f"step env {i}")
+    assert not stats.mismatch, stats.mismatch[:10]
+    assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
+    env.close()
+
+
+def test_autotuned_mapping_is_bit_identical(tmp_path):
+    import torch
+    cfg = W.SCALE["cfg"]
+    seeds = W.seeds(2, 2048)
+    env = U.env_of(cfg, seeds, obs=False)
+    acts = torch.from_numpy(W.actions(2, 8, 2048, 6)).to(env.dev)
+    scratch = torch.empty(env.obs_bytes, dtype=torch.uint8, device=env.dev)
+    cache = str(tmp_path / "tune.txt")
+    snap = env.get_state_bytes()
+    chosen = env.autotune(acts, 8, scratch, cache)
+    assert np.array_equal(env.get_state_bytes(), snap)          # state restored
+    again = env.autotune(acts, 8, scratch, cache)               # cache hit
+    assert again == chosen
+    env.close()
+    _forms_equal(cfg, seeds, None, 8, [("eager", PLAIN1), ("graph", chosen)])
+
+
+def test_checkpoint_resume_bit_identical():
+    import torch
+    cfg = W.KEYDOOR["cfg"]
+    seeds = W.seeds(3, 256)
+    acts = torch.from_numpy(W.actions(3, 150, 256, 6))
+    a = U.env_of(cfg, seeds, obs=False)
+    acts_d = acts.to(a.dev)
+    _run(a, acts_d[:100], 100, "graph", torch)
+    image = a.get_state_bytes()
+    ra = _run(a, acts_d[100:], 50, "eager", torch)
+    b = U.env_of(cfg, seeds, obs=False)           # fresh context
+    b.set_state_bytes(image)
+    rb = _run(b, acts_d[100:], 50, "graph", torch)
+    for k in range(4):
+        assert np.array_equal(ra[k], rb[k])
+    a.close()
+    b.close()
+
+
+def test_edge_cases():
+    import torch
+    from paper_2605_19926_amd import jx
+    cfg = W.TINY["cfg"]
+    # step before reset
+    e = jx.Env(W.seeds(1, 4), cfg)
+    with pytest.raises(jx.JxError) as err:
+        e.step(torch.zeros(4, dtype=torch.uint8, device="cuda"),
+               torch.zeros(4 * 64 * 64 * 3, dtype=torch.uint8, device="cuda"),
+               torch.zeros(4, device="cuda"), torch.zeros(4, dtype=torch.uint8, device="cuda"))
+    assert err.value.code == jx.JX_ESTATE
+    e.reset()
+    # misaligned frame buffer
+    buf = torch.zeros(4 * 64 * 64 * 3 + 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(jx.JxError):
+        e.step(torch.zeros(4, dtype=torch.uint8, device="cuda"), buf[1:])
+    # out-of-range state values are refused on the host
+    S = e.get_state()
+    bad = {"goal": np.array([64, 0, 0, 0], np.int32)}
+    with pytest.raises(jx.JxError):
+        e.set_state(bad)
+    with pytest.raises(jx.JxError):
+        e.set_state({"x": np.array([np.nan, 1.5, 1.5, 1.5], np.float32)})
+    e.close()
+    # zero envs: every call is a no-op
+    z = jx.Env(np.zeros(0, np.uint64), cfg)
+    z.reset()
+    assert z.obs_bytes == 0
+    z.step(torch.zeros(1, dtype=torch.uint8, device="cuda"), torch.zeros(4, dtype=torch.uint8, device="cuda"))
+    z.sync()
+    z.close()
+
+
+def _serve_run(srv, cid, acts, want_obs=True):
+    out = []
+    for t in range(acts.shape[0]):
+        tk = srv.submit(cid, acts[t])
+        out.append(srv.wait(cid, tk, want_obs=want_obs))
+    return out
+
+
+def test_serving_alone_equals_mix_equals_plain():
+    import torch
+    from paper_2605_19926_amd import jx
+    cfg = W.env_cfg(side=24, loop_frac=0.1, goal_sprite=1, obs_h=64, obs_w=64, episode_cap=20)
+    seeds = W.seeds(5, 37)
+    T = 30
+    acts = W.actions(5, T, 37, 6)
+    # plain path
+    env = U.env_of(cfg, seeds, obs=False)
+    plain = _run(env, torch.from_numpy(acts).to(env.dev), T, "eager", torch)
+    env.close()
+    # served alone
+    srv = jx.Server(hbm_budget=1 << 30, n_streams=4)
+    cid, ok = srv.open(seeds, cfg)
+    assert ok
+    alone = _serve_run(srv, cid, acts)
+    srv.close()
+    # served in a mix of concurrent clients of other shapes
+    srv = jx.Server(hbm_budget=1 << 30, n_streams=4)
+    cid, ok = srv.open(seeds, cfg)
+    others = []
+    for k in range(6):
+        c2 = W.env_cfg(side=8 + 9 * k, loop_frac=0.1, key_door=k % 2, goal_sprite=1,
+                       max_decor=2 * (k % 2), obs_h=84 if k % 2 else 64, obs_w=84 if k % 2 else 64)
+        s2 = W.seeds(50 + k, 1 + 40 * k)
+        o, _ = srv.open(s2, c2)
+        others.append((o, W.actions(60 + k, T, len(s2), 6)))
+    results = {}
+
+    def client(o, a):
+        results[o] = _serve_run(srv, o, a, want_obs=False)
+
+    th = [threading.Thread(target=client, args=oa) for oa in others]
+    for t_ in th:
+        t_.start()
+    mix = _serve_run(srv, cid, acts)
+    for t_ in th:
+        t_.join()
+    st = srv.stats()
+    srv.close()
+    n, ob1 = 37, 64 * 64 * 3
+    for t in range(T):
+        p_obs = plain[0][t * n * ob1:(t + 1) * n * ob1].reshape(n, ob1)
+        for res in (alone[t], mix[t]):
+            assert np.array_equal(res[0], p_obs), f"step {t}: frames differ"
+            assert np.array_equal(res[1], plain[1][t * n:(t + 1) * n])
+            assert np.array_equal(res[2], plain[2][t * n:(t + 1) * n])
+    assert st["requests"] >= T * 7
+    assert st["launches"] < st["requests"]          # requests were coalesced
+    assert all(len(v) == T for v in results.values())
+
+
+def test_serving_admission_by_budget():
+    from paper_2605_19926_amd import jx
+    cfg = W.env_cfg(side=32, obs_h=84, obs_w=84)
+    srv = jx.Server(hbm_budget=64 << 20, n_streams=2)
+    ids = []
+    admitted = []
+    for k in range(6):
+        cid, ok = srv.open(W.seeds(70 + k, 200), cfg)   # ~4.5 MB each
+        ids.append(cid)
+        admitted.append(ok)
+    assert all(admitted)
+    big = W.seeds(80, 2000)                              # ~45 MB: must wait
+    cid, ok = srv.open(big, cfg)
+    assert not ok
+    tk = srv.submit(cid, np.zeros(2000, np.uint8))
+    assert srv.wait(cid, tk, timeout=0.2) is None        # still queued for admission
+    for c in ids:
+        srv.close_client(c)
+    res = srv.wait(cid, tk, timeout=60.0)
+    assert res is not None and res[1].shape == (2000,)
+    st = srv.stats()
+    assert st["admission_waits"] >= 1
+    srv.close()
