@@ -97,17 +97,127 @@ def cpu_baseline(wl: dict, envs_per_worker: int = 64, steps: int = 1000) -> dict
             "one_core": one / dt1}
 
 
+def batch_form(jx, torch, launches: list[dict], rollouts: int = 2) -> dict:
+    """Mixed-shape batch (16384 envs: map side {8,16,32,64}, frames {32,64,128}
+    square, key-door on half) stepped by 128-step hipGraph rollouts; env-steps/s
+    per launch mapping."""
+    n, T = W.BATCH["n_envs"], W.BATCH["rollout"]
+    cfgs, idx = W.batch_cfgs(n)
+    env = jx.Env(W.seeds(W.BATCH["number"], n), cfgs, idx)
+    env.reset()
+    ob = env.obs_bytes
+    obs = torch.empty(T * ob, dtype=torch.uint8, device=env.dev)
+    rew = torch.empty(T * n, dtype=torch.float32, device=env.dev)
+    done = torch.empty(T * n, dtype=torch.uint8, device=env.dev)
+    acts = torch.from_numpy(W.actions(W.BATCH["number"], T, n, 6)).to(env.dev)
+    out = {"workload": W.BATCH["name"], "n_envs": n, "rollout": T,
+           "obs_bytes_per_step": ob, "results": []}
+    for launch in launches:
+        env.set_launch(**launch)
+        env.rollout(acts, obs, rew, done, T, obs_stride=ob, graph=True)   # capture + warm
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(rollouts):
+            env.rollout(acts, obs, rew, done, T, obs_stride=ob, graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        steps = rollouts * T
+        out["results"].append({"launch": launch, "env_steps_per_s": n * steps / sec,
+                               "ms_per_step": sec / steps * 1e3,
+                               "obs_gbs": ob * steps / sec / 1e9})
+    env.close()
+    return out
+
+
+def serve_form(jx, n_requests: int, mode: int, n_streams: int = 4) -> dict:
+    """Serving workload: Poisson arrivals (2000 req/s) over 256 client slots,
+    clients of 1-512 envs (log-uniform), side 8-64, frames 64 or 84 square.  An
+    arrival thread submits each request at its time; a collector waits for every
+    ticket (frames, rewards, dones copied to host).  Latency is submit-to-ready
+    as measured by the server."""
+    import threading
+    import queue as q_
+    tr = W.serve_trace(n_requests)
+    srv = jx.Server(hbm_budget=int(64e9), n_streams=n_streams, mode=mode)
+    sessions = {}
+    last_of = {}
+    for k, sid in enumerate(tr["session"]):
+        last_of[int(sid)] = k
+    work: "q_.Queue" = q_.Queue()
+    lat = []
+    env_steps = [0]
+    t_done = [0.0]
+
+    def collector():
+        while True:
+            item = work.get()
+            if item is None:
+                return
+            cid, tk, close = item
+            res = srv.wait(cid, tk, want_obs=True)
+            lat.append(res[3])
+            env_steps[0] += res[1].shape[0]
+            t_done[0] = time.perf_counter()
+            if close:
+                srv.close_client(cid)
+
+    # clients are opened (mazes generated, episode 0 reset on the device) before
+    # the clock starts; requests then arrive on the trace's schedule
+    for k in range(n_requests):
+        sid = int(tr["session"][k])
+        if sid not in sessions:
+            n = int(tr["n_envs"][sid])
+            side = int(tr["side"][sid])
+            ob = int(tr["obs"][sid])
+            cfg = W.env_cfg(side=side, loop_frac=0.1, goal_sprite=1, obs_h=ob, obs_w=ob)
+            seeds = tr["seed_base"][sid] + np.arange(n, dtype=np.uint64)
+            cid, _ = srv.open(seeds, cfg)
+            sessions[sid] = (cid, n)
+    th = threading.Thread(target=collector)
+    th.start()
+    rng = np.random.default_rng(11)
+    t0 = time.perf_counter()
+    for k in range(n_requests):
+        sid = int(tr["session"][k])
+        cid, n = sessions[sid]
+        wait = t0 + float(tr["t"][k]) - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tk = srv.submit(cid, rng.integers(0, 6, size=n, dtype=np.uint8))
+        work.put((cid, tk, last_of[sid] == k))
+    work.put(None)
+    th.join()
+    wall = t_done[0] - t0
+    st = srv.stats()
+    srv.close()
+    lat_ms = np.array(lat) * 1e3
+    return {"mode": "coalesced" if mode == jx.JX_SERVE_COALESCE else "plain-per-request",
+            "streams": n_streams if mode == jx.JX_SERVE_COALESCE else 1,
+            "requests": n_requests, "p50_ms": float(np.percentile(lat_ms, 50)),
+            "p99_ms": float(np.percentile(lat_ms, 99)), "mean_ms": float(lat_ms.mean()),
+            "env_steps_per_s": env_steps[0] / wall, "launches": int(st["launches"]),
+            "offered_req_per_s": W.SERVE["rate"], "wall_s": wall}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10_000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--form", choices=["graph", "eager", "persistent"], default="graph")
+    ap.add_argument("--form", choices=["graph", "eager", "persistent", "pipeline"], default="graph")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0: default)")
+    ap.add_argument("--groups", type=int, default=4, help="persistent form: workgroups per CU")
     ap.add_argument("--store", type=int, default=-1, help="0 normal, 1 non-temporal (-1: default)")
     ap.add_argument("--single-slot", action="store_true", help="write every frame to one slot")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batching and serving forms")
+    ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 launches), to scale "
+                         "HBM traffic counters, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); envs shard "
@@ -116,6 +226,16 @@ def main() -> int:
 
     import torch
     from paper_2605_19926_amd import jx
+
+    if args.calib_copy_mib:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb, "launches": 5}))
+        return 0
 
     wl = W.SCALE
     cfg, n = wl["cfg"], wl["n_envs"]
@@ -130,9 +250,10 @@ def main() -> int:
     acts = torch.from_numpy(W.actions(wl["number"], Wu + K, n, cfg["n_actions"])).to(env.dev)
     rew = torch.empty(RING * n, dtype=torch.float32, device=env.dev)
     done = torch.empty(RING * n, dtype=torch.uint8, device=env.dev)
-    launch = {"form": jx.JX_FORM_PERSISTENT if args.form == "persistent" else jx.JX_FORM_PLAIN,
+    launch = {"form": {"persistent": jx.JX_FORM_PERSISTENT,
+                       "pipeline": jx.JX_FORM_PIPELINE}.get(args.form, jx.JX_FORM_PLAIN),
               "waves_per_group": args.waves or (2 if args.form == "persistent" else 1),
-              "groups_per_cu": 4, "store_mode": max(args.store, 0)}
+              "groups_per_cu": args.groups, "store_mode": max(args.store, 0)}
     env.set_launch(**launch)
     if args.autotune:
         launch = env.autotune(acts, 20, obs[:ob])
@@ -206,6 +327,13 @@ def main() -> int:
         "wall_s": wall,
     }
     env.close()
+    if not args.no_forms:
+        line["batching_form"] = batch_form(jx, torch, [
+            {"form": 0, "waves_per_group": 4, "groups_per_cu": 1, "store_mode": 0},
+            {"form": 1, "waves_per_group": 2, "groups_per_cu": 4, "store_mode": 0},
+            {"form": 2, "waves_per_group": 2, "groups_per_cu": 2, "store_mode": 0}])
+        line["serving_form"] = [serve_form(jx, args.serve_requests, jx.JX_SERVE_COALESCE),
+                                serve_form(jx, args.serve_requests, jx.JX_SERVE_PLAIN)]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)

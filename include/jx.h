@@ -72,11 +72,13 @@ typedef struct jx_ctx jx_ctx;
 
 /* Launch mapping (results are bit-identical under every mapping). */
 #define JX_FORM_PLAIN 0       /* one wave per env, one workgroup slot per env */
-#define JX_FORM_PERSISTENT 1  /* persistent waves pull envs from a device work queue */
+#define JX_FORM_PERSISTENT 1  /* persistent waves pull envs from device work queues */
+#define JX_FORM_PIPELINE 2    /* persistent producer/writer wave pairs, double-buffered */
 typedef struct {
-  int32_t form;            /* JX_FORM_PLAIN or JX_FORM_PERSISTENT */
-  int32_t waves_per_group; /* 1, 2, 4 or 8 waves (envs in flight) per workgroup */
-  int32_t groups_per_cu;   /* persistent form: workgroups launched per compute unit, 1..16 */
+  int32_t form;            /* JX_FORM_PLAIN, JX_FORM_PERSISTENT or JX_FORM_PIPELINE */
+  int32_t waves_per_group; /* waves (plain, persistent: 1, 2, 4, 8) or wave pairs
+                              (pipelined: 1, 2, 4) per workgroup */
+  int32_t groups_per_cu;   /* persistent and pipelined forms: workgroups per compute unit, 1..16 */
   int32_t store_mode;      /* 0: ordinary stores, 1: non-temporal observation stores */
 } jx_launch;
 

@@ -40,6 +40,7 @@ struct jx_ctx {
   int max_side = 0, max_w = 0;
   int n_cu = 1;
   LaunchCfg launch{0, 1, 4, 0};
+  uint32_t seq = 0;  // persistent launches enqueued on this context's stream
   // captured rollouts, keyed by (T, launch mapping)
   std::map<std::array<int32_t, 5>, hipGraphExec_t> graphs;
 };
@@ -130,6 +131,7 @@ Layout make_layout(int n, int n_cfgs, int64_t maps_bytes) {
   L.maps = take(std::max<int64_t>(maps_bytes, 16));
   // after the state image: the rollout descriptor (scratch, not state)
   L.rdesc = take(sizeof(RolloutDesc));
+  L.queues = take(4 * kQueueWords);
   L.total = o;
   return L;
 }
@@ -157,6 +159,7 @@ DevState bind_state(uint8_t* ws, const Layout& L, int n) {
   s.obs_off = (const int64_t*)(ws + L.obs_off);
   s.order = (const int32_t*)(ws + L.order);
   s.rdesc = (RolloutDesc*)(ws + L.rdesc);
+  s.queues = (uint32_t*)(ws + L.queues);
   s.cfgs = (const DevCfg*)(ws + L.cfgs);
   s.maps = ws + L.maps;
   s.hdr = (WsHeader*)(ws + L.hdr);
@@ -242,9 +245,14 @@ jx_status build_image(int n, const uint64_t* seeds, const jx_env_cfg* cfgs, int 
       return set_error(JX_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Enqueues one step/render launch.  seq_override >= 0 fixes the persistent
+// queue sequence number (graph capture); otherwise the context's counter runs.
 static jx_status launch_or_fail(jx_ctx* c, const DevIo& io, hipStream_t st,
-                                const RolloutDesc* rd = nullptr, int t = 0) {
-  int rc = launch_batch(c->S, io, rd, t, c->launch, c->max_side, c->n_cu, st);
+                                const RolloutDesc* rd = nullptr, int t = 0,
+                                int64_t seq_override = -1) {
+  const uint32_t seq = seq_override >= 0 ? (uint32_t)seq_override : c->seq;
+  int rc = launch_batch(c->S, io, rd, t, c->launch, c->max_side, c->n_cu, seq, st);
+  if (rc == 0 && seq_override < 0 && c->launch.form == JX_FORM_PERSISTENT) c->seq += 1;
   if (rc != 0) return set_error(JX_EDEVICE, std::string("kernel launch: ") + kernel_error_string(rc));
   return JX_OK;
 }
@@ -431,7 +439,11 @@ jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs,
     jx_status lst = JX_OK;
     DevIo io{};
     io.mode = MODE_STEP;
-    for (int t = 0; t < T && lst == JX_OK; ++t) lst = launch_or_fail(c, io, c->cap_stream, c->S.rdesc, t);
+    // a kernel (not a memset node) clears the queue counters at the head
+    if (c->launch.form == JX_FORM_PERSISTENT && launch_clear_queues(c->S.queues, c->cap_stream) != 0)
+      lst = set_error(JX_EDEVICE, "queue clear launch failed");
+    for (int t = 0; t < T && lst == JX_OK; ++t)
+      lst = launch_or_fail(c, io, c->cap_stream, c->S.rdesc, t, t);
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (lst != JX_OK) {
       if (g) hipGraphDestroy(g);
@@ -449,6 +461,8 @@ jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs,
     it = c->graphs.emplace(key, ge).first;
   }
   HIPCHK(hipGraphLaunch(it->second, c->stream));
+  // the replay's last launch cleared counter set T % 4: continue from there
+  if (c->launch.form == JX_FORM_PERSISTENT) c->seq = (uint32_t)T;
   return JX_OK;
 }
 
@@ -577,9 +591,11 @@ jx_status jx_set_state(jx_ctx* c, const void* host, size_t bytes) {
 jx_status jx_set_launch(jx_ctx* c, const jx_launch* l) {
   if (!c || !l) return set_error(JX_EINVAL, "null argument");
   const int w = l->waves_per_group;
-  if (l->form != JX_FORM_PLAIN && l->form != JX_FORM_PERSISTENT) return set_error(JX_EINVAL, "bad form");
+  if (l->form != JX_FORM_PLAIN && l->form != JX_FORM_PERSISTENT && l->form != JX_FORM_PIPELINE)
+    return set_error(JX_EINVAL, "bad form");
   if (w != 1 && w != 2 && w != 4 && w != 8) return set_error(JX_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
-  if (l->form == JX_FORM_PERSISTENT && (l->groups_per_cu < 1 || l->groups_per_cu > 16))
+  if (l->form == JX_FORM_PIPELINE && w == 8) return set_error(JX_EINVAL, "pipelined form: 1, 2 or 4 wave pairs");
+  if (l->form != JX_FORM_PLAIN && (l->groups_per_cu < 1 || l->groups_per_cu > 16))
     return set_error(JX_EINVAL, "groups_per_cu must be in 1..16");
   if (l->store_mode != 0 && l->store_mode != 1) return set_error(JX_EINVAL, "store_mode must be 0 or 1");
   c->launch = LaunchCfg{l->form, w, std::max(1, l->groups_per_cu), l->store_mode};
@@ -689,6 +705,9 @@ extern "C" jx_status jx_autotune(jx_ctx* c, const uint8_t* actions, int32_t iter
   for (int w : {1, 2, 4})
     for (int g : {2, 4, 8})
       for (int s : {0, 1}) cands.push_back(LaunchCfg{1, w, g, s});
+  for (int p : {1, 2, 4})
+    for (int g : {1, 2, 4})
+      for (int s : {0, 1}) cands.push_back(LaunchCfg{2, p, g, s});
   const LaunchCfg keep = c->launch;
   std::vector<uint8_t> ref_obs(ob), ref_state(total), ref_io((size_t)iters * n * 5);
   std::vector<uint8_t> cur_obs(ob), cur_state(total), cur_io((size_t)iters * n * 5);

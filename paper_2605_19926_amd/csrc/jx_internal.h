@@ -76,6 +76,7 @@ struct DevState {
   const int64_t* obs_off;  // [n+1]
   const int32_t* order;    // persistent work order (costliest first)
   RolloutDesc* rdesc;      // rollout I/O descriptor
+  uint32_t* queues;        // persistent form: [4 slots][8 queues][32] counters
   const DevCfg* cfgs;
   const uint8_t* maps;
   WsHeader* hdr;
@@ -105,20 +106,28 @@ struct ServeItem {
 // Workspace layout: byte offsets of every array.
 struct Layout {
   int64_t hdr, x, y, th, t, ep, goal, door, key, decor, flags, events, ndecor, invalid, seed,
-      cfg_idx, map_off, obs_off, order, rdesc, cfgs, maps, total;
+      cfg_idx, map_off, obs_off, order, rdesc, queues, cfgs, maps, total;
 };
 
 // Launch entry points implemented in jx_kernels.hip.
 struct LaunchCfg {
   int32_t form, waves_per_group, groups_per_cu, store_mode;
 };
+// Persistent queues: kQueueSlots counter sets of kQueues queues each, one
+// 128-byte line per counter.  Launch `seq` uses set seq % kQueueSlots and clears
+// set (seq + 1) % kQueueSlots for the launch after it.
+constexpr int kQueues = 32, kQueueSlots = 4, kQueueStride = 32;
+constexpr int kQueueWords = kQueues * kQueueSlots * kQueueStride;
+
 // rd != nullptr: the I/O of step t is taken from the device descriptor rd.
+// seq: launch sequence number (persistent form).
 int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t,
-                 const LaunchCfg& lc, int max_side, int n_cu, void* stream);
+                 const LaunchCfg& lc, int max_side, int n_cu, uint32_t seq, void* stream);
+int launch_clear_queues(uint32_t* queues, void* stream);
 int launch_set_desc(RolloutDesc* rd_dev, const RolloutDesc& value, void* stream);
 int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeItem* items_dev,
-                 int n_items, uint32_t* counters_dev, int waves_per_group, int n_groups,
-                 void* stream);
+                 int n_items, uint32_t* queues_dev, uint32_t seq, int waves_per_group,
+                 int n_groups, void* stream);
 const char* kernel_error_string(int code);
 
 }  // namespace jx

@@ -200,23 +200,57 @@ __device__ Episode episode_reset(const DevCfg& cf, const uint8_t* lmap, uint64_t
   return ep;
 }
 
-__device__ __forceinline__ uint32_t pick(uint32_t w, uint32_t sp, int i, uint32_t bg) {
-  return i < (int)(sp >> 24) ? (sp & 0xFFFFFFu) : (i < (int)(w >> 24) ? (w & 0xFFFFFFu) : bg);
+typedef __attribute__((address_space(1))) uint32_t GlobalU32;
+
+// 12 bytes (4 RGB pixels) to global memory; non-temporal on request.
+__device__ __forceinline__ void store12(uint8_t* p, uint32_t a, uint32_t b, uint32_t c, int nt) {
+  if (nt) {
+    GlobalU32* q = (GlobalU32*)p;
+    __builtin_nontemporal_store(a, q);
+    __builtin_nontemporal_store(b, q + 1);
+    __builtin_nontemporal_store(c, q + 2);
+  } else {
+    GlobalU32* q = (GlobalU32*)p;
+    q[0] = a;
+    q[1] = b;
+    q[2] = c;
+  }
 }
 
-struct U3 {
-  uint32_t a, b, c;
+// Pixel colours of one column group (4 columns) at distance index i from the
+// horizon: sprite band, else wall band, else background.  Branch-free.
+struct ColGroup {
+  uint32_t fgS[4], fgW[4], sc[4], cov[4];
 };
-
-__device__ __forceinline__ void store12(uint8_t* p, uint32_t a, uint32_t b, uint32_t c, int nt) {
-  U3* q = reinterpret_cast<U3*>(p);
-  if (nt) {
-    __builtin_nontemporal_store(a, &q->a);
-    __builtin_nontemporal_store(b, &q->b);
-    __builtin_nontemporal_store(c, &q->c);
-  } else {
-    *q = U3{a, b, c};
+__device__ __forceinline__ ColGroup col_group(const uint32_t* lcol, int cq) {
+  const uint4* l4 = reinterpret_cast<const uint4*>(lcol);
+  const uint4 A = l4[2 * cq], B = l4[2 * cq + 1];
+  const uint32_t w[4] = {A.x, A.z, B.x, B.z}, sp[4] = {A.y, A.w, B.y, B.w};
+  ColGroup g;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t wc = w[k] >> 24, scn = sp[k] >> 24;
+    g.fgS[k] = sp[k] & 0xFFFFFFu;
+    g.fgW[k] = w[k] & 0xFFFFFFu;
+    g.sc[k] = scn;
+    g.cov[k] = wc > scn ? wc : scn;
   }
+  return g;
+}
+
+// Writes the mirrored row pair at distance i (row H/2-1-i above, H/2+i below).
+__device__ __forceinline__ void emit_pair(const ColGroup& g, uint32_t i, uint8_t* up, uint8_t* dn,
+                                          int nt) {
+  uint32_t pu[4], pd[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t fg = i < g.sc[k] ? g.fgS[k] : g.fgW[k];
+    const bool c = i < g.cov[k];
+    pu[k] = c ? fg : kCeil;
+    pd[k] = c ? fg : kFloor;
+  }
+  store12(up, pu[0] | (pu[1] << 24), (pu[1] >> 8) | (pu[2] << 16), (pu[2] >> 16) | (pu[3] << 8), nt);
+  store12(dn, pd[0] | (pd[1] << 24), (pd[1] >> 8) | (pd[2] << 16), (pd[2] >> 16) | (pd[3] << 8), nt);
 }
 
 struct ColDbg {
@@ -225,10 +259,11 @@ struct ColDbg {
   int32_t cell;
 };
 
-// Render the env's current state into its frame (and debug records).
-__device__ void render_env(const DevCfg& cf, const DevIo& io, int64_t obs_off, int env, int lane,
-                          uint8_t* lmap, uint32_t* lcol, float x, float y, float th, int goal,
-                          int door, int key, uint32_t fl, int nd, int dec0, int dec1) {
+// Casts the env's columns and reduces each to a span record in lcol (and
+// writes debug records when asked).
+__device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int lane, uint8_t* lmap,
+                               uint32_t* lcol, float x, float y, float th, int goal, int door,
+                               int key, uint32_t fl, int nd, int dec0, int dec1) {
   const int N = cf.side, H = cf.obs_h, W = cf.obs_w, K = cf.n_colors;
   if (door >= 0 && !(fl & FL_DOOR_OPEN) && lane == 0) lmap[door] = 2;
   wave_sync();
@@ -328,49 +363,115 @@ __device__ void render_env(const DevCfg& cf, const DevIo& io, int64_t obs_off, i
     }
   }
   wave_sync();
-  if (!io.obs) return;
+}
 
-  uint8_t* base = io.obs + obs_off;
-  const int Q = W >> 2, G = H * Q, H2 = H >> 1;
-  int row = lane / Q, cq = lane - row * Q;
-  const int dr = 64 / Q, dq = 64 - dr * Q;
-  const uint4* l4 = reinterpret_cast<const uint4*>(lcol);
-  const int nt = io.store_mode;
-  for (int g = lane; g < G; g += 64) {
-    const uint4 A = l4[2 * cq], B = l4[2 * cq + 1];
-    const bool upper = row < H2;
-    const int i = upper ? (H2 - 1 - row) : (row - H2);
-    const uint32_t bg = upper ? kCeil : kFloor;
-    const uint32_t p0 = pick(A.x, A.y, i, bg), p1 = pick(A.z, A.w, i, bg);
-    const uint32_t p2 = pick(B.x, B.y, i, bg), p3 = pick(B.z, B.w, i, bg);
-    store12(base + 12 * (int64_t)g, p0 | (p1 << 24), (p1 >> 8) | (p2 << 16), (p2 >> 16) | (p3 << 8),
-            nt);
-    row += dr;
-    cq += dq;
-    if (cq >= Q) {
-      cq -= Q;
-      ++row;
+// Expands the span records into the frame, one mirrored row pair per lane and
+// iteration: lane -> (column group cq, distance i from the horizon).
+__device__ void fill_frame(const uint32_t* lcol, uint8_t* base, int W, int H, int lane, int nt) {
+  const int Q = W >> 2, H2 = H >> 1, G2 = H2 * Q;
+  const int rowb = 3 * W;
+  int i = lane / Q, cq = lane - i * Q;
+  const int di = 64 / Q, dq = 64 - di * Q;
+  if (dq == 0) {
+    // the lane's column group is fixed: keep its records in registers
+    if (lane < G2) {
+      const ColGroup g = col_group(lcol, cq);
+      uint8_t* up = base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq;
+      uint8_t* dn = base + (int64_t)(H2 + i) * rowb + 12 * cq;
+      const int64_t step = (int64_t)di * rowb;
+      for (; i < H2; i += di) {
+        emit_pair(g, (uint32_t)i, up, dn, nt);
+        up -= step;
+        dn += step;
+      }
+    }
+  } else {
+    for (int k = lane; k < G2; k += 64) {
+      const ColGroup g = col_group(lcol, cq);
+      emit_pair(g, (uint32_t)i, base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq,
+                base + (int64_t)(H2 + i) * rowb + 12 * cq, nt);
+      i += di;
+      cq += dq;
+      if (cq >= Q) {
+        cq -= Q;
+        ++i;
+      }
     }
   }
 }
 
-// The whole per-env pipeline.  All lanes run the uniform parts redundantly;
-// lane 0 writes the scalar results with vector stores.
-__device__ void process_env(const DevState& S, const DevIo& io, int env, int lane, uint8_t* lmap,
-                            uint32_t* lcol) {
-  const DevCfg cf = S.cfgs[S.cfg_idx[env]];
-  const int N = cf.side, NN = N * N;
-  const uint32_t* gm = reinterpret_cast<const uint32_t*>(S.maps + S.map_off[env]);
-  uint32_t* lm32 = reinterpret_cast<uint32_t*>(lmap);
-  for (int i = lane; i < ((NN + 3) >> 2); i += 64) lm32[i] = gm[i];
+// Everything one env-step produces, handed from the computing wave to the
+// wave that writes it back (or kept by the same wave in the plain form).
+struct EnvOut {
+  int64_t obs_off;
+  int env, W, H, mode;
+  float x, y, th, reward;
+  uint32_t t, ep, fl, nd, ev, done;
+  int goal, door, key, dec0, dec1;
+};
 
-  float x = S.x[env], y = S.y[env], th = S.th[env];
-  uint32_t t = S.t[env], ep = S.ep[env];
-  int goal = S.goal[env], door = S.door[env], key = S.key[env];
-  int dec0 = S.decor[2 * env], dec1 = S.decor[2 * env + 1];
-  uint32_t fl = S.flags[env];
-  int nd = S.ndecor[env];
-  const uint64_t seed = S.seed[env];
+// Inputs of one env-step, loaded ahead of use: the configuration and state
+// (uniform, scalar loads) and this lane's share of the map's dwords.
+template <int MAXN>
+struct EnvIn {
+  static constexpr int kMapWords = (MAXN * MAXN + 255) / 256;  // dwords per lane
+  DevCfg cf;
+  int env;
+  float x, y, th;
+  uint32_t t, ep, fl;
+  int goal, door, key, dec0, dec1, nd;
+  uint64_t seed;
+  uint32_t map[kMapWords];
+};
+
+template <int MAXN>
+__device__ __forceinline__ void load_env(const DevState& S, int env, int lane, EnvIn<MAXN>& in) {
+  in.env = env;
+  in.cf = S.cfgs[S.cfg_idx[env]];
+  const int NN = in.cf.side * in.cf.side;
+  const uint32_t* gm = reinterpret_cast<const uint32_t*>(S.maps + S.map_off[env]);
+#pragma unroll
+  for (int k = 0; k < EnvIn<MAXN>::kMapWords; ++k) {
+    const int i = lane + 64 * k;
+    in.map[k] = (i < ((NN + 3) >> 2)) ? gm[i] : 0u;
+  }
+  in.x = S.x[env];
+  in.y = S.y[env];
+  in.th = S.th[env];
+  in.t = S.t[env];
+  in.ep = S.ep[env];
+  in.goal = S.goal[env];
+  in.door = S.door[env];
+  in.key = S.key[env];
+  in.dec0 = S.decor[2 * env];
+  in.dec1 = S.decor[2 * env + 1];
+  in.fl = S.flags[env];
+  in.nd = S.ndecor[env];
+  in.seed = S.seed[env];
+}
+
+// Stage, step, reset and column cast of one env from its loaded inputs: LDS
+// and registers only, no global stores (so a wave doing only this never waits
+// on outstanding stores).  All lanes run the uniform parts redundantly.
+template <int MAXN>
+__device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevIo& io, int lane,
+                            uint8_t* lmap, uint32_t* lcol, EnvOut& o) {
+  const DevCfg& cf = in.cf;
+  const int env = in.env;
+  const int N = cf.side, NN = N * N;
+  uint32_t* lm32 = reinterpret_cast<uint32_t*>(lmap);
+#pragma unroll
+  for (int k = 0; k < EnvIn<MAXN>::kMapWords; ++k) {
+    const int i = lane + 64 * k;
+    if (i < ((NN + 3) >> 2)) lm32[i] = in.map[k];
+  }
+  float x = in.x, y = in.y, th = in.th;
+  uint32_t t = in.t, ep = in.ep;
+  int goal = in.goal, door = in.door, key = in.key;
+  int dec0 = in.dec0, dec1 = in.dec1;
+  uint32_t fl = in.fl;
+  int nd = in.nd;
+  const uint64_t seed = in.seed;
   wave_sync();
 
   const int mode = io.mode;
@@ -458,28 +559,63 @@ __device__ void process_env(const DevState& S, const DevIo& io, int env, int lan
     if (done) ev |= EV_RESET;
   }
   if (io.obs || io.dbg)
-    render_env(cf, io, S.obs_off[env], env, lane, lmap, lcol, x, y, th, goal, door, key, fl, nd,
-               dec0, dec1);
-  if (lane == 0 && mode != MODE_RENDER) {
-    S.x[env] = x;
-    S.y[env] = y;
-    S.th[env] = th;
-    S.t[env] = t;
-    S.ep[env] = ep;
-    S.goal[env] = goal;
-    S.door[env] = door;
-    S.key[env] = key;
-    S.decor[2 * env] = dec0;
-    S.decor[2 * env + 1] = dec1;
-    S.flags[env] = (uint8_t)fl;
-    S.ndecor[env] = (uint8_t)nd;
-    S.events[env] = (uint8_t)ev;
-    if (ev & EV_INVALID) S.invalid[env] += 1u;
-    if (mode == MODE_STEP) {
-      io.rew[env] = reward;
-      io.done[env] = done ? 1 : 0;
-    }
+    render_columns(cf, io, env, lane, lmap, lcol, x, y, th, goal, door, key, fl, nd, dec0, dec1);
+  o.obs_off = S.obs_off[env];
+  o.env = env;
+  o.W = cf.obs_w;
+  o.H = cf.obs_h;
+  o.mode = mode;
+  o.x = x;
+  o.y = y;
+  o.th = th;
+  o.reward = reward;
+  o.t = t;
+  o.ep = ep;
+  o.fl = fl;
+  o.nd = (uint32_t)nd;
+  o.ev = ev;
+  o.done = done ? 1u : 0u;
+  o.goal = goal;
+  o.door = door;
+  o.key = key;
+  o.dec0 = dec0;
+  o.dec1 = dec1;
+}
+
+// Scalar results of one env-step, stored by lane 0 with vector stores.
+__device__ void write_back(const DevState& S, const DevIo& io, const EnvOut& o, int lane) {
+  if (lane != 0 || o.mode == MODE_RENDER) return;
+  const int env = o.env;
+  S.x[env] = o.x;
+  S.y[env] = o.y;
+  S.th[env] = o.th;
+  S.t[env] = o.t;
+  S.ep[env] = o.ep;
+  S.goal[env] = o.goal;
+  S.door[env] = o.door;
+  S.key[env] = o.key;
+  S.decor[2 * env] = o.dec0;
+  S.decor[2 * env + 1] = o.dec1;
+  S.flags[env] = (uint8_t)o.fl;
+  S.ndecor[env] = (uint8_t)o.nd;
+  S.events[env] = (uint8_t)o.ev;
+  if (o.ev & EV_INVALID) S.invalid[env] += 1u;
+  if (o.mode == MODE_STEP) {
+    io.rew[env] = o.reward;
+    io.done[env] = (uint8_t)o.done;
   }
+}
+
+// The whole per-env pipeline in one wave.
+template <int MAXN>
+__device__ void process_env(const DevState& S, const DevIo& io, int env, int lane, uint8_t* lmap,
+                            uint32_t* lcol) {
+  EnvIn<MAXN> in;
+  load_env<MAXN>(S, env, lane, in);
+  EnvOut o;
+  produce_env<MAXN>(in, S, io, lane, lmap, lcol, o);
+  if (io.obs) fill_frame(lcol, io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
+  write_back(S, io, o, lane);
 }
 
 // I/O of this launch: given by value, or (graph replays) from the descriptor.
@@ -504,63 +640,148 @@ __global__ __launch_bounds__(64 * WPB) void k_plain(DevState S, DevIo io0, const
   const int env = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + w);
   if (env >= S.n) return;
   const DevIo io = io_of(io0, rd, t);
-  process_env(S, io, env, lane, smap[w], scol[w]);
+  process_env<MAXN>(S, io, env, lane, smap[w], scol[w]);
 }
 
-// Persistent form: each wave pulls env indices (costliest first) from the
-// workspace queue until it runs dry.  The last wave to leave zeroes the queue
-// for the next launch, so consecutive launches and graph replays need no reset.
+// Work distribution of the persistent forms.  Items (positions in a work
+// order) are split over up to 32 queues by position modulo the queue count; a
+// workgroup serves queue blockIdx % nq (so each queue is served from one XCD),
+// and the queues (one 128-byte line each) sit in different L2 channels: their
+// atomics do not serialize on one address.  Each wave first takes one chunk statically, then claims further
+// chunks with one atomic each.  Launch `seq` counts in counter set seq % 4 and
+// clears set (seq + 1) % 4 for the next launch on the same stream.
+struct QueueView {
+  uint32_t* ctr;      // this queue's counter
+  int q, nq;          // queue index and count
+  int items;          // items in this queue
+  int waves, wave;    // waves serving it and this wave's rank among them
+  int chunk;
+};
+
+template <int WPB>
+__device__ __forceinline__ QueueView queue_view(uint32_t* queues, uint32_t seq, int n_items, int w,
+                                                int lane) {
+  QueueView v;
+  const int grid = (int)gridDim.x;
+  v.nq = grid < kQueues ? grid : kQueues;
+  v.q = (int)blockIdx.x % v.nq;
+  const int slot = (int)(seq % kQueueSlots);
+  v.ctr = queues + (slot * kQueues + v.q) * kQueueStride;
+  v.items = n_items > v.q ? (n_items - v.q + v.nq - 1) / v.nq : 0;
+  v.waves = ((grid - v.q + v.nq - 1) / v.nq) * WPB;
+  v.wave = ((int)blockIdx.x / v.nq) * WPB + w;
+  const int c = v.items / (2 * v.waves);
+  v.chunk = c < 1 ? 1 : c;
+  if (blockIdx.x == 0 && w == 0 && lane < kQueues) {
+    const int nxt = (int)((seq + 1) % kQueueSlots);
+    queues[(nxt * kQueues + lane) * kQueueStride] = 0u;
+  }
+  return v;
+}
+
+// Calls f(position) for every item position this wave owns or claims.  Every
+// wave leaves once its claim passes the end of its queue.
+template <typename F>
+__device__ __forceinline__ void queue_drain(const QueueView& v, int lane, F&& f) {
+  const int dyn0 = v.waves * v.chunk;  // first position handed out by the counter
+  int first = v.wave * v.chunk;        // static first chunk
+  while (first < v.items) {
+    const int end = min(first + v.chunk, v.items);
+    for (int j = first; j < end; ++j) f(v.q + j * v.nq);
+    if (dyn0 >= v.items) break;        // the static chunks cover the queue
+    // a plain read first: a drained queue costs no atomic
+    uint32_t cur = 0;
+    if (lane == 0) cur = __hip_atomic_load(v.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (dyn0 + __builtin_amdgcn_readfirstlane((int)cur) >= v.items) break;
+    uint32_t got = 0;
+    if (lane == 0) got = atomicAdd(v.ctr, (uint32_t)v.chunk);
+    first = dyn0 + __builtin_amdgcn_readfirstlane((int)got);
+  }
+}
+
 template <int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_persist(DevState S, DevIo io0, const RolloutDesc* rd,
-                                                      int t, int total_waves) {
+                                                      int t, uint32_t seq) {
   __shared__ __align__(16) uint8_t smap[WPB][kMaxSide * kMaxSide];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  WsHeader* h = S.hdr;
   const DevIo io = io_of(io0, rd, t);
-  for (;;) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(&h->queue, 1u);
-    item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
-    if (item >= (uint32_t)S.n) break;
-    const int env = __builtin_amdgcn_readfirstlane(S.order[item]);
-    process_env(S, io, env, lane, smap[w], scol[w]);
-  }
-  if (lane == 0) {
-    __threadfence();
-    if (atomicAdd(&h->exited, 1u) == (uint32_t)total_waves - 1u) {
-      atomicExch(&h->queue, 0u);
-      atomicExch(&h->exited, 0u);
-    }
-  }
+  const QueueView v = queue_view<WPB>(S.queues, seq, S.n, w, lane);
+  queue_drain(v, lane, [&](int pos) {
+    const int env = __builtin_amdgcn_readfirstlane(S.order[pos]);
+    process_env<kMaxSide>(S, io, env, lane, smap[w], scol[w]);
+  });
 }
 
 // Serving form: work items span several clients' batches.
 template <int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_serve(const DevState* states, const DevIo* ios,
                                                     const ServeItem* items, int n_items,
-                                                    uint32_t* counters, int total_waves) {
+                                                    uint32_t* queues, uint32_t seq) {
   __shared__ __align__(16) uint8_t smap[WPB][kMaxSide * kMaxSide];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  for (;;) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(&counters[0], 1u);
-    item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
-    if (item >= (uint32_t)n_items) break;
-    const int d = __builtin_amdgcn_readfirstlane(items[item].desc);
-    const int env = __builtin_amdgcn_readfirstlane(items[item].env);
+  const QueueView v = queue_view<WPB>(queues, seq, n_items, w, lane);
+  queue_drain(v, lane, [&](int pos) {
+    const int d = __builtin_amdgcn_readfirstlane(items[pos].desc);
+    const int env = __builtin_amdgcn_readfirstlane(items[pos].env);
     const DevState S = states[d];
     const DevIo io = ios[d];
-    process_env(S, io, env, lane, smap[w], scol[w]);
-  }
-  if (lane == 0) {
-    __threadfence();
-    if (atomicAdd(&counters[1], 1u) == (uint32_t)total_waves - 1u) {
-      atomicExch(&counters[0], 0u);
-      atomicExch(&counters[1], 0u);
+    process_env<kMaxSide>(S, io, env, lane, smap[w], scol[w]);
+  });
+}
+
+// Pipelined form: a workgroup holds P wave pairs.  In each pair a producer
+// wave loads, steps and casts envs (prefetching the next env's inputs while it
+// computes the current one) and never stores to global memory; a writer wave
+// expands the previous env's span records into its frame and stores frame and
+// state.  The two alternate LDS buffers, one workgroup barrier per round, so
+// producing env k+1 overlaps writing env k, and the writer's outstanding stores
+// never stall a load.  Pairs walk the work order (costliest first) with a
+// static stride of all pairs in the grid.
+template <int MAXN, int P>
+__global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const RolloutDesc* rd,
+                                                  int t) {
+  __shared__ __align__(16) uint8_t smap[P][MAXN * MAXN];
+  __shared__ __align__(16) uint32_t scol[P][2][2 * kMaxW];
+  __shared__ EnvOut sout[P][2];
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int pair = w >> 1;
+  const bool writer = (w & 1) != 0;
+  const DevIo io = io_of(io0, rd, t);
+  const int pairs = (int)gridDim.x * P;
+  const int gp = (int)blockIdx.x * P + pair;
+  const int lead = (int)blockIdx.x * P;  // the workgroup's pair with the most items
+  const int rounds = S.n > lead ? (S.n - lead + pairs - 1) / pairs : 0;
+  EnvIn<MAXN> cur, nxt;
+  if (!writer && gp < S.n) load_env<MAXN>(S, __builtin_amdgcn_readfirstlane(S.order[gp]), lane, cur);
+  for (int k = 0; k <= rounds; ++k) {
+    const int b = k & 1;
+    if (!writer) {
+      const int item = gp + k * pairs;
+      if (k < rounds && item < S.n) {
+        const int nitem = item + pairs;
+        if (nitem < S.n) load_env<MAXN>(S, __builtin_amdgcn_readfirstlane(S.order[nitem]), lane, nxt);
+        EnvOut o;
+        produce_env<MAXN>(cur, S, io, lane, smap[pair], scol[pair][b], o);
+        if (lane == 0) sout[pair][b] = o;
+        cur = nxt;
+      } else if (lane == 0) {
+        sout[pair][b].env = -1;
+      }
+    } else if (k > 0) {
+      const EnvOut o = sout[pair][b ^ 1];
+      if (o.env >= 0) {
+        fill_frame(scol[pair][b ^ 1], io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
+        write_back(S, io, o, lane);
+      }
     }
+    __syncthreads();
   }
+}
+
+__global__ void k_clear_queues(uint32_t* q) {
+  for (int i = (int)threadIdx.x; i < kQueueWords; i += (int)blockDim.x) q[i] = 0u;
 }
 
 __global__ void k_set_desc(RolloutDesc* rd, RolloutDesc v) {
@@ -583,14 +804,37 @@ int launch_plain_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, in
 
 }  // namespace
 
+// Reset, render-only and debug launches always take the plain kernel.
+inline bool mode_needs_plain(const DevIo& io, const RolloutDesc* rd) {
+  return !rd && (io.mode != MODE_STEP || io.dbg != nullptr || io.obs == nullptr);
+}
+
+template <int MAXN>
+int launch_pipe_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int p, int groups,
+                  hipStream_t st) {
+  switch (p) {
+    case 1: hipLaunchKernelGGL((k_pipe<MAXN, 1>), dim3(groups), dim3(128), 0, st, s, io, rd, t); break;
+    case 2: hipLaunchKernelGGL((k_pipe<MAXN, 2>), dim3(groups), dim3(256), 0, st, s, io, rd, t); break;
+    case 4: hipLaunchKernelGGL((k_pipe<MAXN, 4>), dim3(groups), dim3(512), 0, st, s, io, rd, t); break;
+    default: return -1;
+  }
+  return (int)hipGetLastError();
+}
+
 int launch_set_desc(RolloutDesc* rd_dev, const RolloutDesc& value, void* stream) {
   hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), rd_dev,
                      value);
   return (int)hipGetLastError();
 }
 
+int launch_clear_queues(uint32_t* queues, void* stream) {
+  hipLaunchKernelGGL(k_clear_queues, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                     queues);
+  return (int)hipGetLastError();
+}
+
 int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t,
-                 const LaunchCfg& lc, int max_side, int n_cu, void* stream) {
+                 const LaunchCfg& lc, int max_side, int n_cu, uint32_t seq, void* stream) {
   if (s.n <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int wpb = lc.waves_per_group;
@@ -599,32 +843,41 @@ int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int 
     if (max_side <= 32) return launch_plain_n<32>(s, io, rd, t, wpb, st);
     return launch_plain_n<64>(s, io, rd, t, wpb, st);
   }
+  if (lc.form == 2) {
+    // waves_per_group counts wave pairs (1, 2 or 4) in the pipelined form
+    const int p = wpb > 4 ? 4 : wpb;
+    int groups = n_cu * lc.groups_per_cu;
+    const int need = (s.n + p - 1) / p;
+    if (groups > need) groups = need;
+    if (groups < 1) groups = 1;
+    if (mode_needs_plain(io, rd)) return launch_plain_n<64>(s, io, rd, t, 1, st);
+    if (max_side <= 16) return launch_pipe_n<16>(s, io, rd, t, p, groups, st);
+    if (max_side <= 32) return launch_pipe_n<32>(s, io, rd, t, p, groups, st);
+    return launch_pipe_n<64>(s, io, rd, t, p, groups, st);
+  }
   int groups = n_cu * lc.groups_per_cu;
   const int need = (s.n + wpb - 1) / wpb;
   if (groups > need) groups = need;
   if (groups < 1) groups = 1;
-  const int waves = groups * wpb;
   switch (wpb) {
-    case 1: hipLaunchKernelGGL((k_persist<1>), dim3(groups), dim3(64), 0, st, s, io, rd, t, waves); break;
-    case 2: hipLaunchKernelGGL((k_persist<2>), dim3(groups), dim3(128), 0, st, s, io, rd, t, waves); break;
-    case 4: hipLaunchKernelGGL((k_persist<4>), dim3(groups), dim3(256), 0, st, s, io, rd, t, waves); break;
-    case 8: hipLaunchKernelGGL((k_persist<8>), dim3(groups), dim3(512), 0, st, s, io, rd, t, waves); break;
+    case 1: hipLaunchKernelGGL((k_persist<1>), dim3(groups), dim3(64), 0, st, s, io, rd, t, seq); break;
+    case 2: hipLaunchKernelGGL((k_persist<2>), dim3(groups), dim3(128), 0, st, s, io, rd, t, seq); break;
+    case 4: hipLaunchKernelGGL((k_persist<4>), dim3(groups), dim3(256), 0, st, s, io, rd, t, seq); break;
+    case 8: hipLaunchKernelGGL((k_persist<8>), dim3(groups), dim3(512), 0, st, s, io, rd, t, seq); break;
     default: return -1;
   }
   return (int)hipGetLastError();
 }
 
 int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeItem* items_dev,
-                 int n_items, uint32_t* counters_dev, int waves_per_group, int n_groups,
-                 void* stream) {
+                 int n_items, uint32_t* queues_dev, uint32_t seq, int waves_per_group,
+                 int n_groups, void* stream) {
   if (n_items <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int wpb = waves_per_group;
-  const int waves = n_groups * wpb;
-  switch (wpb) {
-    case 1: hipLaunchKernelGGL((k_serve<1>), dim3(n_groups), dim3(64), 0, st, states_dev, ios_dev, items_dev, n_items, counters_dev, waves); break;
-    case 2: hipLaunchKernelGGL((k_serve<2>), dim3(n_groups), dim3(128), 0, st, states_dev, ios_dev, items_dev, n_items, counters_dev, waves); break;
-    case 4: hipLaunchKernelGGL((k_serve<4>), dim3(n_groups), dim3(256), 0, st, states_dev, ios_dev, items_dev, n_items, counters_dev, waves); break;
+  switch (waves_per_group) {
+    case 1: hipLaunchKernelGGL((k_serve<1>), dim3(n_groups), dim3(64), 0, st, states_dev, ios_dev, items_dev, n_items, queues_dev, seq); break;
+    case 2: hipLaunchKernelGGL((k_serve<2>), dim3(n_groups), dim3(128), 0, st, states_dev, ios_dev, items_dev, n_items, queues_dev, seq); break;
+    case 4: hipLaunchKernelGGL((k_serve<4>), dim3(n_groups), dim3(256), 0, st, states_dev, ios_dev, items_dev, n_items, queues_dev, seq); break;
     default: return -1;
   }
   return (int)hipGetLastError();

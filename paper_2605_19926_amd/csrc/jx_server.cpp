@@ -130,7 +130,8 @@ struct StreamSlot {
   DevState* d_states = nullptr;
   DevIo* d_ios = nullptr;
   ServeItem* d_items = nullptr;
-  uint32_t* d_counters = nullptr;
+  uint32_t* d_counters = nullptr;   // queue counter sets of this stream
+  uint32_t seq = 0;                  // serving launches issued on this stream
   DevState* h_states = nullptr;
   DevIo* h_ios = nullptr;
   ServeItem* h_items = nullptr;
@@ -212,7 +213,7 @@ jx_status activate(jx_server* s, Client* c) {
     return set_error(JX_EDEVICE, "client upload failed");
   DevIo io{};
   io.mode = MODE_RESET;
-  int rc = launch_batch(c->S, io, nullptr, 0, LaunchCfg{0, 1, 1, 0}, c->cfg.side, s->n_cu, s->admin);
+  int rc = launch_batch(c->S, io, nullptr, 0, LaunchCfg{0, 1, 1, 0}, c->cfg.side, s->n_cu, 0, s->admin);
   if (rc) return set_error(JX_EDEVICE, std::string("client reset: ") + kernel_error_string(rc));
   if (hipStreamSynchronize(s->admin) != hipSuccess) return set_error(JX_EDEVICE, "client reset sync failed");
   return JX_OK;
@@ -300,7 +301,7 @@ void issue(jx_server* s, int k, std::vector<Client*>& batch) {
     ok = ok && hipMemcpyAsync((void*)c->io.act, c->h_act, c->n, hipMemcpyHostToDevice, st) == hipSuccess;
   if (s->mode == JX_SERVE_PLAIN) {
     Client* c = batch[0];
-    ok = ok && launch_batch(c->S, c->io, nullptr, 0, LaunchCfg{0, 1, 1, 0}, c->cfg.side, s->n_cu, st) == 0;
+    ok = ok && launch_batch(c->S, c->io, nullptr, 0, LaunchCfg{0, 1, 1, 0}, c->cfg.side, s->n_cu, 0, st) == 0;
   } else {
     ok = ok && hipMemcpyAsync(ss.d_states, ss.h_states, sizeof(DevState) * batch.size(),
                               hipMemcpyHostToDevice, st) == hipSuccess;
@@ -311,7 +312,9 @@ void issue(jx_server* s, int k, std::vector<Client*>& batch) {
     const int wpb = 2;
     int groups = std::min((n_items + wpb - 1) / wpb, s->n_cu * 4);
     groups = std::max(groups, 1);
-    ok = ok && launch_serve(ss.d_states, ss.d_ios, ss.d_items, n_items, ss.d_counters, wpb, groups, st) == 0;
+    ok = ok && launch_serve(ss.d_states, ss.d_ios, ss.d_items, n_items, ss.d_counters, ss.seq, wpb,
+                            groups, st) == 0;
+    if (ok) ss.seq += 1;
   }
   for (Client* c : batch) {
     ok = ok && hipMemcpyAsync(c->h_obs, c->io.obs, c->obs_bytes, hipMemcpyDeviceToHost, st) == hipSuccess;
@@ -452,8 +455,8 @@ jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_by
     SRV_CHK(hipMalloc((void**)&ss.d_states, sizeof(DevState) * kMaxClientsPerLaunch), "alloc");
     SRV_CHK(hipMalloc((void**)&ss.d_ios, sizeof(DevIo) * kMaxClientsPerLaunch), "alloc");
     SRV_CHK(hipMalloc((void**)&ss.d_items, sizeof(ServeItem) * kMaxItemsPerLaunch), "alloc");
-    SRV_CHK(hipMalloc((void**)&ss.d_counters, 256), "alloc");
-    SRV_CHK(hipMemset(ss.d_counters, 0, 256), "memset");
+    SRV_CHK(hipMalloc((void**)&ss.d_counters, 4 * kQueueWords), "alloc");
+    SRV_CHK(hipMemset(ss.d_counters, 0, 4 * kQueueWords), "memset");
     SRV_CHK(hipHostMalloc((void**)&ss.h_states, sizeof(DevState) * kMaxClientsPerLaunch), "pinned");
     SRV_CHK(hipHostMalloc((void**)&ss.h_ios, sizeof(DevIo) * kMaxClientsPerLaunch), "pinned");
     SRV_CHK(hipHostMalloc((void**)&ss.h_items, sizeof(ServeItem) * kMaxItemsPerLaunch), "pinned");

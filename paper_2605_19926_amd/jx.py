@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjx.so")
 
 JX_OK, JX_EINVAL, JX_ENOMEM, JX_EDEVICE, JX_ESTATE, JX_EBUSY = 0, -1, -2, -3, -4, -5
-JX_FORM_PLAIN, JX_FORM_PERSISTENT = 0, 1
+JX_FORM_PLAIN, JX_FORM_PERSISTENT, JX_FORM_PIPELINE = 0, 1, 2
 JX_ROLLOUT_GRAPH = 1
 JX_SERVE_COALESCE, JX_SERVE_PLAIN = 0, 1
 

@@ -64,7 +64,10 @@ def test_graph_eager_persistent_identical():
                 ("graph", dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0)),
                 ("graph", dict(form=1, waves_per_group=2, groups_per_cu=2, store_mode=0)),
                 ("graph", dict(form=1, waves_per_group=4, groups_per_cu=8, store_mode=1)),
-                ("eager", dict(form=1, waves_per_group=1, groups_per_cu=1, store_mode=0))]
+                ("eager", dict(form=1, waves_per_group=1, groups_per_cu=1, store_mode=0)),
+                ("graph", dict(form=2, waves_per_group=1, groups_per_cu=1, store_mode=0)),
+                ("eager", dict(form=2, waves_per_group=2, groups_per_cu=2, store_mode=1)),
+                ("graph", dict(form=2, waves_per_group=4, groups_per_cu=4, store_mode=0))]
     _forms_equal(cfg, seeds, None, 40, launches)
 
 
@@ -97,7 +100,9 @@ def test_mixed_shapes_batch_identical_and_oracle():
     seeds = W.seeds(W.BATCH["number"], n)
     launches = [("eager", PLAIN1),
                 ("graph", dict(form=1, waves_per_group=2, groups_per_cu=4, store_mode=0)),
-                ("graph", dict(form=1, waves_per_group=1, groups_per_cu=8, store_mode=1))]
+                ("graph", dict(form=1, waves_per_group=1, groups_per_cu=8, store_mode=1)),
+                ("graph", dict(form=2, waves_per_group=2, groups_per_cu=1, store_mode=0)),
+                ("eager", dict(form=2, waves_per_group=4, groups_per_cu=2, store_mode=1))]
     _forms_equal(cfgs, seeds, idx, 12, launches)
     # oracle parity of the mixed batch from shared states (render + one step)
     env = U.env_of(cfgs, seeds, idx, obs=False)
