@@ -113,18 +113,21 @@ def batch_form(jx, torch, launches: list[dict], rollouts: int = 2) -> dict:
     out = {"workload": W.BATCH["name"], "n_envs": n, "rollout": T,
            "obs_bytes_per_step": ob, "results": []}
     for launch in launches:
+        launch = dict(launch)
+        fused = launch.pop("fused", False)
         env.set_launch(**launch)
-        env.rollout(acts, obs, rew, done, T, obs_stride=ob, graph=True)   # capture + warm
+        env.rollout(acts, obs, rew, done, T, obs_stride=ob, graph=not fused, fused=fused)  # warm
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(rollouts):
-            env.rollout(acts, obs, rew, done, T, obs_stride=ob, graph=True)
+            env.rollout(acts, obs, rew, done, T, obs_stride=ob, graph=not fused, fused=fused)
         e1.record()
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3
         steps = rollouts * T
-        out["results"].append({"launch": launch, "env_steps_per_s": n * steps / sec,
+        out["results"].append({"launch": launch, "rollout": "fused" if fused else "graph",
+                               "env_steps_per_s": n * steps / sec,
                                "ms_per_step": sec / steps * 1e3,
                                "obs_gbs": ob * steps / sec / 1e9})
     env.close()
@@ -206,8 +209,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10_000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--form", choices=["graph", "eager", "persistent", "pipeline"], default="graph")
-    ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0: default)")
+    ap.add_argument("--form", choices=["fused", "graph", "eager", "persistent", "pipeline"],
+                    default="fused")
+    ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0: the form's default)")
     ap.add_argument("--groups", type=int, default=4, help="persistent form: workgroups per CU")
     ap.add_argument("--store", type=int, default=-1, help="0 normal, 1 non-temporal (-1: default)")
     ap.add_argument("--single-slot", action="store_true", help="write every frame to one slot")
@@ -252,7 +256,7 @@ def main() -> int:
     done = torch.empty(RING * n, dtype=torch.uint8, device=env.dev)
     launch = {"form": {"persistent": jx.JX_FORM_PERSISTENT,
                        "pipeline": jx.JX_FORM_PIPELINE}.get(args.form, jx.JX_FORM_PLAIN),
-              "waves_per_group": args.waves or (2 if args.form == "persistent" else 1),
+              "waves_per_group": args.waves or {"persistent": 2, "fused": 8}.get(args.form, 4),
               "groups_per_cu": args.groups, "store_mode": max(args.store, 0)}
     env.set_launch(**launch)
     if args.autotune:
@@ -276,10 +280,11 @@ def main() -> int:
             else:
                 o = obs[slot * ob:] if slots > 1 else obs
                 env.rollout(acts[t:t + chunk], o, rew[slot * n:], done[slot * n:], chunk,
-                            obs_stride=ob if slots > 1 else 0, graph=True)
+                            obs_stride=ob if slots > 1 else 0, graph=args.form != "fused",
+                            fused=args.form == "fused")
 
     # capture every graph length the timed region will use before timing
-    if args.form != "eager":
+    if args.form not in ("eager", "fused"):
         for T in sorted({c for _, _, c in plan(Wu, K)}):
             env.rollout(acts[:T], obs, rew, done, T, obs_stride=ob if slots > 1 else 0, graph=True)
     run(0, Wu)
@@ -329,6 +334,7 @@ def main() -> int:
     env.close()
     if not args.no_forms:
         line["batching_form"] = batch_form(jx, torch, [
+            {"form": 0, "waves_per_group": 4, "groups_per_cu": 1, "store_mode": 0, "fused": True},
             {"form": 0, "waves_per_group": 4, "groups_per_cu": 1, "store_mode": 0},
             {"form": 1, "waves_per_group": 2, "groups_per_cu": 4, "store_mode": 0},
             {"form": 2, "waves_per_group": 2, "groups_per_cu": 2, "store_mode": 0}])

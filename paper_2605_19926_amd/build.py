@@ -25,7 +25,7 @@ HOST_SOURCES = ["jx_abi.cpp", "jx_layout.cpp", "jx_server.cpp"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
 DEVICE_FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops", "-fno-gpu-rdc"]
-HOST_FLAGS = ["-D__HIP_PLATFORM_AMD__"]
+HOST_FLAGS = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-Wno-unused-result", "-Wno-unused-value"]
 
 
 def _obj_dir() -> str:

@@ -1,7 +1,7 @@
 // jx_abi.cpp -- host runtime behind include/jx.h: validation, workspace layout,
 // reset (host maze generation + device episode reset), step, hipGraph rollouts,
 // state import/export and the launch-mapping autotuner.
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include <algorithm>
 #include <chrono>
@@ -137,6 +137,21 @@ Layout make_layout(int n, int n_cfgs, int64_t maps_bytes) {
 }
 
 int64_t map_bytes_of(int side) { return align_up((int64_t)side * side, 16); }
+
+// Marks a batch whose envs all use one configuration (the common case): the
+// kernels then read the configuration from the kernel argument and compute map
+// and frame offsets from the env index.
+void set_uniform(DevState* s, const jx_env_cfg* cfgs, int n_cfgs, const std::vector<int32_t>& idx) {
+  bool one = n_cfgs >= 1;
+  for (size_t i = 1; i < idx.size() && one; ++i) one = idx[i] == idx[0];
+  s->uniform = 0;
+  if (!one || idx.empty()) return;
+  const jx_env_cfg& c = cfgs[idx[0]];
+  s->uniform = 1;
+  s->ucfg = derive_cfg(c);
+  s->map_stride = map_bytes_of(c.side);
+  s->obs_stride = (int64_t)c.obs_h * c.obs_w * 3;
+}
 
 DevState bind_state(uint8_t* ws, const Layout& L, int n) {
   DevState s{};
@@ -354,6 +369,7 @@ jx_status jx_reset(jx_ctx* c, int32_t n_envs, const uint64_t* seeds, const jx_en
     c->max_side = std::max(c->max_side, cfgs[k].side);
     c->max_w = std::max(c->max_w, cfgs[k].obs_w);
   }
+  set_uniform(&c->S, cfgs, n_cfgs, idx);
   DevIo io{};
   io.obs = obs_dev;
   io.mode = MODE_RESET;
@@ -411,6 +427,14 @@ jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs,
   if (obs_stride < 0 || (obs_stride != 0 && obs_stride < ob) || (obs_stride & 3) || ((uintptr_t)obs & 3))
     return set_error(JX_EINVAL, "obs_stride must be 0 or >= jx_obs_bytes(), 4-byte aligned");
   HIPCHK(hipSetDevice(c->device));
+  if (flags & JX_ROLLOUT_FUSED) {
+    LaunchCfg lc = c->launch;
+    if (lc.form != JX_FORM_PLAIN || lc.waves_per_group > 8) lc = LaunchCfg{0, 4, 1, lc.store_mode};
+    int rc = launch_rollout_fused(c->S, actions, obs, obs_stride, reward, done, T, lc, c->max_side,
+                                  c->n_cu, c->stream);
+    if (rc) return set_error(JX_EDEVICE, std::string("fused rollout launch: ") + kernel_error_string(rc));
+    return JX_OK;
+  }
   if (!(flags & JX_ROLLOUT_GRAPH)) {
     for (int t = 0; t < T; ++t) {
       DevIo io{};
@@ -556,6 +580,13 @@ jx_status jx_set_state(jx_ctx* c, const void* host, size_t bytes) {
     return set_error(JX_EINVAL, "state image configuration differs from this context");
   // every index the kernels dereference must be in range
   const Layout& L = c->L;
+  int64_t expect_moff = 0;
+  for (int i = 0; i < c->n; ++i) {
+    uint32_t mo;
+    std::memcpy(&mo, b + L.map_off + 4 * i, 4);
+    if ((int64_t)mo != expect_moff) return set_error(JX_EINVAL, "state image: map offsets differ from this context");
+    expect_moff += map_bytes_of(c->cfgs[c->cfg_idx[i]].side);
+  }
   for (int i = 0; i < c->n; ++i) {
     const int N = c->cfgs[c->cfg_idx[i]].side;
     const int NN = N * N;
@@ -575,6 +606,12 @@ jx_status jx_set_state(jx_ctx* c, const void* host, size_t bytes) {
               x < (float)N && y < (float)N && nd <= kMaxDecor && b[L.flags + i] <= 3 &&
               moff + (uint64_t)NN <= (uint64_t)(L.rdesc - L.maps);
     for (int k = 0; k < 5; ++k) ok = ok && ids[k] >= -1 && ids[k] < NN;
+    if (ok) {
+      // every border tile of the map must block (the walks rely on it)
+      const uint8_t* m = b + L.maps + moff;
+      for (int k = 0; k < N && ok; ++k)
+        ok = m[k] && m[(N - 1) * N + k] && m[k * N] && m[k * N + N - 1];
+    }
     for (int k = 0; k < nd; ++k) ok = ok && ids[3 + k] >= 0;
     if (!ok) return set_error(JX_EINVAL, "state image: env " + std::to_string(i) + " holds an out-of-range value");
   }

@@ -13,6 +13,7 @@ DevCfg derive_cfg(const jx_env_cfg& c);
 Layout make_layout(int n, int n_cfgs, int64_t maps_bytes);
 int64_t map_bytes_of(int side);
 DevState bind_state(uint8_t* ws, const Layout& L, int n);
+void set_uniform(DevState* s, const jx_env_cfg* cfgs, int n_cfgs, const std::vector<int32_t>& idx);
 jx_status build_image(int n, const uint64_t* seeds, const jx_env_cfg* cfgs, int n_cfgs,
                       const int32_t* cfg_index, std::vector<uint8_t>* img, Layout* L,
                       std::vector<int64_t>* obs_off, std::vector<int32_t>* idx);

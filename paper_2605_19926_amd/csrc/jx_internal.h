@@ -76,12 +76,17 @@ struct DevState {
   const int64_t* obs_off;  // [n+1]
   const int32_t* order;    // persistent work order (costliest first)
   RolloutDesc* rdesc;      // rollout I/O descriptor
-  uint32_t* queues;        // persistent form: [4 slots][8 queues][32] counters
+  uint32_t* queues;        // persistent form: [4 slots][32 queues][32] counters
   const DevCfg* cfgs;
   const uint8_t* maps;
   WsHeader* hdr;
   int32_t n;
-  int32_t pad;
+  // One configuration for every env: the kernels take it from here and derive
+  // map and frame offsets from the env index (no dependent loads).
+  int32_t uniform;
+  DevCfg ucfg;
+  int64_t map_stride;
+  int64_t obs_stride;
 };
 
 // Per-launch I/O.
@@ -124,6 +129,10 @@ constexpr int kQueueWords = kQueues * kQueueSlots * kQueueStride;
 int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t,
                  const LaunchCfg& lc, int max_side, int n_cu, uint32_t seq, void* stream);
 int launch_clear_queues(uint32_t* queues, void* stream);
+// One launch for T steps of every env (actions for all steps given up front).
+int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride,
+                         float* rew, uint8_t* dn, int T, const LaunchCfg& lc, int max_side, int n_cu,
+                         void* stream);
 int launch_set_desc(RolloutDesc* rd_dev, const RolloutDesc& value, void* stream);
 int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeItem* items_dev,
                  int n_items, uint32_t* queues_dev, uint32_t seq, int waves_per_group,

@@ -221,6 +221,7 @@ __device__ __forceinline__ void store12(uint8_t* p, uint32_t a, uint32_t b, uint
 // horizon: sprite band, else wall band, else background.  Branch-free.
 struct ColGroup {
   uint32_t fgS[4], fgW[4], sc[4], cov[4];
+  uint32_t any;  // rows at distance < any hold a wall or sprite pixel in this group
 };
 __device__ __forceinline__ ColGroup col_group(const uint32_t* lcol, int cq) {
   const uint4* l4 = reinterpret_cast<const uint4*>(lcol);
@@ -235,12 +236,27 @@ __device__ __forceinline__ ColGroup col_group(const uint32_t* lcol, int cq) {
     g.sc[k] = scn;
     g.cov[k] = wc > scn ? wc : scn;
   }
+  const uint32_t a = g.cov[0] > g.cov[1] ? g.cov[0] : g.cov[1];
+  const uint32_t b = g.cov[2] > g.cov[3] ? g.cov[2] : g.cov[3];
+  g.any = a > b ? a : b;
   return g;
 }
 
+constexpr uint32_t kCeil3[3] = {kCeil | (kCeil << 24), (kCeil >> 8) | (kCeil << 16),
+                                (kCeil >> 16) | (kCeil << 8)};
+constexpr uint32_t kFloor3[3] = {kFloor | (kFloor << 24), (kFloor >> 8) | (kFloor << 16),
+                                 (kFloor >> 16) | (kFloor << 8)};
+
 // Writes the mirrored row pair at distance i (row H/2-1-i above, H/2+i below).
+// When no lane of the wave has a wall or sprite pixel at its distance, the
+// whole wave stores the constant ceiling and floor patterns.
 __device__ __forceinline__ void emit_pair(const ColGroup& g, uint32_t i, uint8_t* up, uint8_t* dn,
                                           int nt) {
+  if (__ballot(i < g.any) == 0ull) {
+    store12(up, kCeil3[0], kCeil3[1], kCeil3[2], nt);
+    store12(dn, kFloor3[0], kFloor3[1], kFloor3[2], nt);
+    return;
+  }
   uint32_t pu[4], pd[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -301,7 +317,7 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
     const float camX = (float)(2 * col + 1 - W) / (float)W;
     const float rx = fmaf(camX, px, cs);
     const float ry = fmaf(camX, py, sn);
-    int ix = ix0, iy = iy0;
+    const int ix = ix0, iy = iy0;
     const int stx = rx > 0.f ? 1 : -1, sty = ry > 0.f ? 1 : -1;
     float Xn = (float)(rx > 0.f ? ix + 1 : ix);
     float Yn = (float)(ry > 0.f ? iy + 1 : iy);
@@ -310,24 +326,26 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
     float ty = ry != 0.f ? (Yn - y) * ivy : INF;
     float tst = INF;
     int side = 0, hit = -1, cell = 1;
+    // Branch-free walk: every lane crosses one grid line per iteration.  The
+    // tile index moves by +-1 (x crossing) or +-N (y crossing); the border of
+    // blocking tiles (checked on the host) stops every walk inside the map.
+    const float fsx = (float)stx, fsy = (float)sty;
+    const int dy = sty * N, NN = N * N;
+    int id = iy * N + ix;
     for (int it = 0; it < 4 * N + 8; ++it) {
-      if (tx < ty) {
-        ix += stx;
-        tst = tx;
-        side = 0;
-        Xn += (float)stx;
-        tx = (Xn - x) * ivx;
-      } else {
-        iy += sty;
-        tst = ty;
-        side = 1;
-        Yn += (float)sty;
-        ty = (Yn - y) * ivy;
-      }
-      if ((unsigned)ix >= (unsigned)N || (unsigned)iy >= (unsigned)N) break;
-      const int v = lmap[iy * N + ix];
+      const bool sx = tx < ty;
+      tst = sx ? tx : ty;
+      side = sx ? 0 : 1;
+      id += sx ? stx : dy;
+      Xn += sx ? fsx : 0.f;
+      Yn += sx ? 0.f : fsy;
+      const float ntx = (Xn - x) * ivx, nty = (Yn - y) * ivy;
+      tx = sx ? ntx : tx;
+      ty = sx ? ty : nty;
+      if ((unsigned)id >= (unsigned)NN) break;
+      const int v = lmap[id];
       if (v) {
-        hit = iy * N + ix;
+        hit = id;
         cell = v;
         break;
       }
@@ -427,9 +445,10 @@ struct EnvIn {
 template <int MAXN>
 __device__ __forceinline__ void load_env(const DevState& S, int env, int lane, EnvIn<MAXN>& in) {
   in.env = env;
-  in.cf = S.cfgs[S.cfg_idx[env]];
+  in.cf = S.uniform ? S.ucfg : S.cfgs[S.cfg_idx[env]];
   const int NN = in.cf.side * in.cf.side;
-  const uint32_t* gm = reinterpret_cast<const uint32_t*>(S.maps + S.map_off[env]);
+  const uint8_t* mp = S.uniform ? S.maps + (int64_t)env * S.map_stride : S.maps + S.map_off[env];
+  const uint32_t* gm = reinterpret_cast<const uint32_t*>(mp);
 #pragma unroll
   for (int k = 0; k < EnvIn<MAXN>::kMapWords; ++k) {
     const int i = lane + 64 * k;
@@ -453,9 +472,10 @@ __device__ __forceinline__ void load_env(const DevState& S, int env, int lane, E
 // Stage, step, reset and column cast of one env from its loaded inputs: LDS
 // and registers only, no global stores (so a wave doing only this never waits
 // on outstanding stores).  All lanes run the uniform parts redundantly.
+// action < 0: read this env's action from io.act.
 template <int MAXN>
-__device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevIo& io, int lane,
-                            uint8_t* lmap, uint32_t* lcol, EnvOut& o) {
+__device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevIo& io, int action,
+                            int lane, uint8_t* lmap, uint32_t* lcol, EnvOut& o) {
   const DevCfg& cf = in.cf;
   const int env = in.env;
   const int N = cf.side, NN = N * N;
@@ -479,7 +499,7 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   uint32_t ev = 0;
   bool done = false;
   if (mode == MODE_STEP) {
-    const int a = io.act[env];
+    const int a = action >= 0 ? action : io.act[env];
     float sn, cs;
     sincosf(th, &sn, &cs);
     float mvx = 0.f, mvy = 0.f, dth = 0.f;
@@ -560,7 +580,7 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   }
   if (io.obs || io.dbg)
     render_columns(cf, io, env, lane, lmap, lcol, x, y, th, goal, door, key, fl, nd, dec0, dec1);
-  o.obs_off = S.obs_off[env];
+  o.obs_off = S.uniform ? (int64_t)env * S.obs_stride : S.obs_off[env];
   o.env = env;
   o.W = cf.obs_w;
   o.H = cf.obs_h;
@@ -613,7 +633,7 @@ __device__ void process_env(const DevState& S, const DevIo& io, int env, int lan
   EnvIn<MAXN> in;
   load_env<MAXN>(S, env, lane, in);
   EnvOut o;
-  produce_env<MAXN>(in, S, io, lane, lmap, lcol, o);
+  produce_env<MAXN>(in, S, io, -1, lane, lmap, lcol, o);
   if (io.obs) fill_frame(lcol, io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
   write_back(S, io, o, lane);
 }
@@ -763,7 +783,7 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
         const int nitem = item + pairs;
         if (nitem < S.n) load_env<MAXN>(S, __builtin_amdgcn_readfirstlane(S.order[nitem]), lane, nxt);
         EnvOut o;
-        produce_env<MAXN>(cur, S, io, lane, smap[pair], scol[pair][b], o);
+        produce_env<MAXN>(cur, S, io, -1, lane, smap[pair], scol[pair][b], o);
         if (lane == 0) sout[pair][b] = o;
         cur = nxt;
       } else if (lane == 0) {
@@ -777,6 +797,82 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
       }
     }
     __syncthreads();
+  }
+}
+
+// Fused rollout: each wave carries its env through all T steps of a rollout
+// with the state in registers and the map words in registers (restaged into
+// LDS every step), after loading the env's T actions up front.  Inside the
+// step loop the wave issues no global loads, so its frame stores never stall
+// it, and waves drift out of phase: one wave's casting overlaps another's
+// stores.  Waves take envs by a static stride over the work order.  Per step
+// the results are those of a single-step launch; the state is written back
+// once, after the last step.
+template <int MAXN, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* act, uint8_t* obs,
+                                                   int64_t obs_stride, float* rew, uint8_t* dn,
+                                                   int T, int store_mode) {
+  __shared__ __align__(16) uint8_t smap[WPB][MAXN * MAXN];
+  __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int waves = (int)gridDim.x * WPB;
+  const int64_t n = S.n;
+  DevIo io{};
+  io.obs = obs;
+  io.mode = MODE_STEP;
+  io.store_mode = store_mode;
+  for (int item = (int)blockIdx.x * WPB + w; item < S.n; item += waves) {
+    const int env = __builtin_amdgcn_readfirstlane(S.order[item]);
+    EnvIn<MAXN> in;
+    load_env<MAXN>(S, env, lane, in);
+    uint32_t n_invalid = 0;
+    EnvOut o;
+    for (int t0 = 0; t0 < T; t0 += 128) {
+      // lane l holds the actions of steps t0 + l and t0 + 64 + l
+      const int s0 = t0 + lane, s1 = t0 + 64 + lane;
+      const uint32_t a0 = s0 < T ? act[(int64_t)s0 * n + env] : 0u;
+      const uint32_t a1 = s1 < T ? act[(int64_t)s1 * n + env] : 0u;
+      const int tend = T - t0 < 128 ? T - t0 : 128;
+      for (int k = 0; k < tend; ++k) {
+        const int a = __shfl((int)(k < 64 ? a0 : a1), k & 63, 64);
+        produce_env<MAXN>(in, S, io, a, lane, smap[w], scol[w], o);
+        const int t = t0 + k;
+        fill_frame(scol[w], obs + (int64_t)t * obs_stride + o.obs_off, o.W, o.H, lane, store_mode);
+        if (lane == 0) {
+          rew[(int64_t)t * n + env] = o.reward;
+          dn[(int64_t)t * n + env] = (uint8_t)o.done;
+        }
+        n_invalid += (o.ev & EV_INVALID) ? 1u : 0u;
+        in.x = o.x;
+        in.y = o.y;
+        in.th = o.th;
+        in.t = o.t;
+        in.ep = o.ep;
+        in.fl = o.fl;
+        in.nd = (int)o.nd;
+        in.goal = o.goal;
+        in.door = o.door;
+        in.key = o.key;
+        in.dec0 = o.dec0;
+        in.dec1 = o.dec1;
+      }
+    }
+    if (lane == 0 && T > 0) {
+      S.x[env] = o.x;
+      S.y[env] = o.y;
+      S.th[env] = o.th;
+      S.t[env] = o.t;
+      S.ep[env] = o.ep;
+      S.goal[env] = o.goal;
+      S.door[env] = o.door;
+      S.key[env] = o.key;
+      S.decor[2 * env] = o.dec0;
+      S.decor[2 * env + 1] = o.dec1;
+      S.flags[env] = (uint8_t)o.fl;
+      S.ndecor[env] = (uint8_t)o.nd;
+      S.events[env] = (uint8_t)o.ev;
+      if (n_invalid) S.invalid[env] += n_invalid;
+    }
   }
 }
 
@@ -816,6 +912,19 @@ int launch_pipe_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int
     case 1: hipLaunchKernelGGL((k_pipe<MAXN, 1>), dim3(groups), dim3(128), 0, st, s, io, rd, t); break;
     case 2: hipLaunchKernelGGL((k_pipe<MAXN, 2>), dim3(groups), dim3(256), 0, st, s, io, rd, t); break;
     case 4: hipLaunchKernelGGL((k_pipe<MAXN, 4>), dim3(groups), dim3(512), 0, st, s, io, rd, t); break;
+    default: return -1;
+  }
+  return (int)hipGetLastError();
+}
+
+template <int MAXN>
+int launch_roll_n(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride, float* rew,
+                  uint8_t* dn, int T, int wpb, int groups, int nt, hipStream_t st) {
+  switch (wpb) {
+    case 1: hipLaunchKernelGGL((k_roll<MAXN, 1>), dim3(groups), dim3(64), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
+    case 2: hipLaunchKernelGGL((k_roll<MAXN, 2>), dim3(groups), dim3(128), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
+    case 4: hipLaunchKernelGGL((k_roll<MAXN, 4>), dim3(groups), dim3(256), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
+    case 8: hipLaunchKernelGGL((k_roll<MAXN, 8>), dim3(groups), dim3(512), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
     default: return -1;
   }
   return (int)hipGetLastError();
@@ -881,6 +990,21 @@ int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeIt
     default: return -1;
   }
   return (int)hipGetLastError();
+}
+
+int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride,
+                         float* rew, uint8_t* dn, int T, const LaunchCfg& lc, int max_side, int n_cu,
+                         void* stream) {
+  if (s.n <= 0 || T <= 0) return 0;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int wpb = lc.waves_per_group;
+  // one wave per env while they fit on the chip (16 waves per CU), else a stride
+  int groups = (s.n + wpb - 1) / wpb;
+  const int cap = n_cu * (16 / wpb > 0 ? 16 / wpb : 1);
+  if (groups > cap) groups = cap;
+  if (max_side <= 16) return launch_roll_n<16>(s, act, obs, obs_stride, rew, dn, T, wpb, groups, lc.store_mode, st);
+  if (max_side <= 32) return launch_roll_n<32>(s, act, obs, obs_stride, rew, dn, T, wpb, groups, lc.store_mode, st);
+  return launch_roll_n<64>(s, act, obs, obs_stride, rew, dn, T, wpb, groups, lc.store_mode, st);
 }
 
 const char* kernel_error_string(int code) { return hipGetErrorString((hipError_t)code); }

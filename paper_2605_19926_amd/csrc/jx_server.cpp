@@ -12,7 +12,7 @@
 //                   results out of its client's pinned buffers and completes it
 // A request that arrives while launches are in flight joins the next launch,
 // which can start on another stream before the earlier ones finish.
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include <algorithm>
 #include <chrono>
@@ -143,8 +143,42 @@ constexpr int kMaxItemsPerLaunch = 1 << 18;
 
 }  // namespace
 
+// Pinned host buffers are recycled, not freed: freeing pinned memory can
+// synchronise the device, which would stall every client's requests.
+class PinnedPool {
+ public:
+  void* get(size_t bytes) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = free_.lower_bound(bytes);
+    if (it != free_.end() && it->first <= 2 * bytes + 4096) {
+      void* p = it->second;
+      size_[p] = it->first;
+      free_.erase(it);
+      return p;
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes) != hipSuccess) return nullptr;
+    size_[p] = bytes;
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    free_.emplace(size_[p], p);
+  }
+  ~PinnedPool() {
+    for (auto& kv : free_) (void)hipHostFree(kv.second);
+  }
+
+ private:
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;
+  std::map<void*, size_t> size_;
+};
+
 struct jx_server {
   int device = 0;
+  PinnedPool pinned;
   int mode = JX_SERVE_COALESCE;
   int max_batch_envs = 0;
   int n_cu = 1;
@@ -198,17 +232,18 @@ jx_status activate(jx_server* s, Client* c) {
   uint8_t* dn = rew + align256(4 * (int64_t)c->n);
   c->L = L;
   c->S = bind_state(ws, L, c->n);
+  set_uniform(&c->S, &c->cfg, 1, idx);
   c->io = DevIo{};
   c->io.act = act;
   c->io.obs = obs;
   c->io.rew = (float*)rew;
   c->io.done = dn;
   c->io.mode = MODE_STEP;
-  if (hipHostMalloc((void**)&c->h_act, std::max(c->n, 1)) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_obs, std::max<int64_t>(c->obs_bytes, 1)) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_rew, 4 * std::max(c->n, 1)) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_done, std::max(c->n, 1)) != hipSuccess)
-    return set_error(JX_ENOMEM, "pinned host buffers");
+  c->h_act = (uint8_t*)s->pinned.get(std::max(c->n, 1));
+  c->h_obs = (uint8_t*)s->pinned.get(std::max<int64_t>(c->obs_bytes, 1));
+  c->h_rew = (float*)s->pinned.get(4 * (size_t)std::max(c->n, 1));
+  c->h_done = (uint8_t*)s->pinned.get(std::max(c->n, 1));
+  if (!c->h_act || !c->h_obs || !c->h_rew || !c->h_done) return set_error(JX_ENOMEM, "pinned host buffers");
   if (hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, s->admin) != hipSuccess)
     return set_error(JX_EDEVICE, "client upload failed");
   DevIo io{};
@@ -222,10 +257,10 @@ jx_status activate(jx_server* s, Client* c) {
 void free_client_memory(jx_server* s, Client* c) {
   if (c->arena_off >= 0) s->arena.release(c->arena_off, c->bytes);
   c->arena_off = -1;
-  if (c->h_act) hipHostFree(c->h_act);
-  if (c->h_obs) hipHostFree(c->h_obs);
-  if (c->h_rew) hipHostFree(c->h_rew);
-  if (c->h_done) hipHostFree(c->h_done);
+  s->pinned.put(c->h_act);
+  s->pinned.put(c->h_obs);
+  s->pinned.put(c->h_rew);
+  s->pinned.put(c->h_done);
   c->h_act = c->h_obs = c->h_done = nullptr;
   c->h_rew = nullptr;
 }
@@ -390,19 +425,30 @@ void completion_main(jx_server* s) {
     lk.lock();
     Launch L = std::move(s->inflight.front());
     s->inflight.pop_front();
-    for (auto& r : L.reqs) {
-      auto it = s->clients.find(r->client);
-      Client* c = it == s->clients.end() ? nullptr : it->second.get();
+    // Copy the results out of the clients' pinned buffers without the lock:
+    // those clients stay in flight (no new launch touches their buffers) until
+    // the copies are done.
+    std::vector<Client*> owners(L.reqs.size(), nullptr);
+    for (size_t k = 0; k < L.reqs.size(); ++k) {
+      auto it = s->clients.find(L.reqs[k]->client);
+      owners[k] = it == s->clients.end() ? nullptr : it->second.get();
+    }
+    lk.unlock();
+    for (size_t k = 0; k < L.reqs.size(); ++k) {
+      Request* r = L.reqs[k].get();
+      Client* c = owners[k];
       if (e == hipSuccess && c) {
         r->obs.assign(c->h_obs, c->h_obs + c->obs_bytes);
         r->rew.assign(c->h_rew, c->h_rew + c->n);
         r->done.assign(c->h_done, c->h_done + c->n);
-        r->status = 2;
-      } else {
-        r->status = 3;
       }
+    }
+    lk.lock();
+    for (size_t k = 0; k < L.reqs.size(); ++k) {
+      Request* r = L.reqs[k].get();
+      r->status = (e == hipSuccess && owners[k]) ? 2 : 3;
       r->t_done = t;
-      if (c) c->in_flight = false;
+      if (owners[k]) owners[k]->in_flight = false;
       s->stats.requests += 1;
     }
     if (e != hipSuccess) s->fatal = std::string("device error: ") + hipGetErrorString(e);
@@ -561,18 +607,24 @@ jx_status jx_server_submit(jx_server* s, int32_t client, const uint8_t* actions,
 jx_status jx_server_wait(jx_server* s, uint64_t ticket, double timeout_s, uint8_t* obs, float* rew,
                          uint8_t* done, double* latency) {
   if (!s) return set_error(JX_EINVAL, "null server");
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->requests.find(ticket);
-  if (it == s->requests.end()) return set_error(JX_EINVAL, "unknown ticket");
-  std::shared_ptr<Request> r = it->second;
-  auto finished = [&] { return r->status >= 2; };
-  if (timeout_s < 0) {
-    s->cv_done.wait(lk, finished);
-  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), finished)) {
-    return JX_EBUSY;
+  std::shared_ptr<Request> r;
+  std::string fatal;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return set_error(JX_EINVAL, "unknown ticket");
+    r = it->second;
+    auto finished = [&] { return r->status >= 2; };
+    if (timeout_s < 0) {
+      s->cv_done.wait(lk, finished);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), finished)) {
+      return JX_EBUSY;
+    }
+    s->requests.erase(ticket);
+    fatal = s->fatal;
   }
-  s->requests.erase(ticket);
-  if (r->status == 3) return set_error(JX_EDEVICE, s->fatal.empty() ? "request failed" : s->fatal);
+  // the request is ours alone now: copy without the lock
+  if (r->status == 3) return set_error(JX_EDEVICE, fatal.empty() ? "request failed" : fatal);
   if (obs) std::memcpy(obs, r->obs.data(), r->obs.size());
   if (rew) std::memcpy(rew, r->rew.data(), 4 * r->rew.size());
   if (done) std::memcpy(done, r->done.data(), r->done.size());

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libjx.so")
 
 JX_OK, JX_EINVAL, JX_ENOMEM, JX_EDEVICE, JX_ESTATE, JX_EBUSY = 0, -1, -2, -3, -4, -5
 JX_FORM_PLAIN, JX_FORM_PERSISTENT, JX_FORM_PIPELINE = 0, 1, 2
-JX_ROLLOUT_GRAPH = 1
+JX_ROLLOUT_GRAPH, JX_ROLLOUT_FUSED = 1, 2
 JX_SERVE_COALESCE, JX_SERVE_PLAIN = 0, 1
 
 EV_BLOCKED_X, EV_BLOCKED_Y, EV_KEY, EV_GOAL = 0x01, 0x02, 0x04, 0x08
@@ -230,9 +230,11 @@ class Env:
         check(lib().jx_step(self.ctx, _ptr(actions), _ptr(obs), _ptr(reward), _ptr(done)))
         return reward, done
 
-    def rollout(self, actions, obs, reward, done, T: int, obs_stride: int = 0, graph: bool = True):
+    def rollout(self, actions, obs, reward, done, T: int, obs_stride: int = 0, graph: bool = True,
+                fused: bool = False):
+        flags = (JX_ROLLOUT_GRAPH if graph else 0) | (JX_ROLLOUT_FUSED if fused else 0)
         check(lib().jx_rollout(self.ctx, T, _ptr(actions), _ptr(obs), obs_stride, _ptr(reward),
-                               _ptr(done), JX_ROLLOUT_GRAPH if graph else 0))
+                               _ptr(done), flags))
 
     def render(self, obs=None, debug=None):
         check(lib().jx_render(self.ctx, _ptr(obs), _ptr(debug)))

@@ -26,6 +26,8 @@ def _run(env, acts_d, T, mode, torch):
             env.step(acts_d[t], obs[t * ob:(t + 1) * ob], rew[t * n:(t + 1) * n], done[t * n:(t + 1) * n])
     elif mode == "rollout_eager":
         env.rollout(acts_d, obs, rew, done, T, obs_stride=ob, graph=False)
+    elif mode == "fused":
+        env.rollout(acts_d, obs, rew, done, T, obs_stride=ob, graph=False, fused=True)
     else:
         env.rollout(acts_d, obs, rew, done, T, obs_stride=ob, graph=True)
     torch.cuda.synchronize()
@@ -67,8 +69,20 @@ def test_graph_eager_persistent_identical():
                 ("eager", dict(form=1, waves_per_group=1, groups_per_cu=1, store_mode=0)),
                 ("graph", dict(form=2, waves_per_group=1, groups_per_cu=1, store_mode=0)),
                 ("eager", dict(form=2, waves_per_group=2, groups_per_cu=2, store_mode=1)),
-                ("graph", dict(form=2, waves_per_group=4, groups_per_cu=4, store_mode=0))]
+                ("graph", dict(form=2, waves_per_group=4, groups_per_cu=4, store_mode=0)),
+                ("fused", dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0)),
+                ("fused", dict(form=0, waves_per_group=1, groups_per_cu=1, store_mode=1))]
     _forms_equal(cfg, seeds, None, 40, launches)
+
+
+def test_fused_rollout_long_and_resets():
+    """More than 128 steps (two action windows) across episode ends."""
+    cfg = W.env_cfg(side=12, loop_frac=0.1, goal_sprite=1, key_door=1, max_decor=2,
+                    episode_cap=37, obs_h=32, obs_w=32)
+    seeds = W.seeds(12, 300)
+    _forms_equal(cfg, seeds, None, 200, [("eager", PLAIN1),
+                                         ("fused", dict(form=0, waves_per_group=8, groups_per_cu=1,
+                                                        store_mode=0))])
 
 
 def test_graph_replays_agree_with_eager():
@@ -102,7 +116,8 @@ def test_mixed_shapes_batch_identical_and_oracle():
                 ("graph", dict(form=1, waves_per_group=2, groups_per_cu=4, store_mode=0)),
                 ("graph", dict(form=1, waves_per_group=1, groups_per_cu=8, store_mode=1)),
                 ("graph", dict(form=2, waves_per_group=2, groups_per_cu=1, store_mode=0)),
-                ("eager", dict(form=2, waves_per_group=4, groups_per_cu=2, store_mode=1))]
+                ("eager", dict(form=2, waves_per_group=4, groups_per_cu=2, store_mode=1)),
+                ("fused", dict(form=0, waves_per_group=2, groups_per_cu=1, store_mode=0))]
     _forms_equal(cfgs, seeds, idx, 12, launches)
     # oracle parity of the mixed batch from shared states (render + one step)
     env = U.env_of(cfgs, seeds, idx, obs=False)
@@ -204,6 +219,13 @@ def test_edge_cases():
         e.set_state(bad)
     with pytest.raises(jx.JxError):
         e.set_state({"x": np.array([np.nan, 1.5, 1.5, 1.5], np.float32)})
+    # a map whose border does not block is refused (the walks rely on it)
+    lay = e.state_layout()
+    img = e.get_state_bytes()
+    off = lay["maps"][0] + int(S["map_offset"][2])
+    img[off + 3] = 0                                        # row 0 of env 2's map
+    with pytest.raises(jx.JxError):
+        e.set_state_bytes(img)
     e.close()
     # zero envs: every call is a no-op
     z = jx.Env(np.zeros(0, np.uint64), cfg)
