@@ -31,19 +31,53 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 RING = 128
 
 
-def algorithmic_bytes(cfg: dict) -> dict:
-    """HBM bytes one env-step must move at minimum (per env)."""
+def algorithmic_bytes(cfg: dict, steps_per_launch: int = 1) -> dict:
+    """HBM bytes one env must move at minimum, per env-step, when one launch
+    advances it `steps_per_launch` steps.  Frames, actions, rewards and done
+    flags move every step; the layout and the state are read once and the
+    state written once per launch."""
     N = cfg["side"]
+    T = max(1, steps_per_launch)
     obs = cfg["obs_h"] * cfg["obs_w"] * 3
     map_read = (N * N + 15) // 16 * 16
     # x y theta t episode goal door key (8 x 4) + decor (8) + flags, n_decor (2)
-    # + seed (8) + cfg index, map offset (8) + frame offset (8) + action (1)
-    state_read = 32 + 8 + 2 + 8 + 8 + 8 + 1
+    # + seed (8) + cfg index, map offset (8) + frame offset (8)
+    state_read = 32 + 8 + 2 + 8 + 8 + 8
     # x y theta t episode goal door key (32) + decor (8) + flags, n_decor, events (3)
-    # + reward (4) + done (1)
-    state_write = 32 + 8 + 3 + 4 + 1
+    state_write = 32 + 8 + 3
+    per_step = obs + 1 + 4 + 1  # frame, action, reward, done
+    once = map_read + state_read + state_write
     return {"obs": obs, "map": map_read, "state_read": state_read, "state_write": state_write,
-            "total": obs + map_read + state_read + state_write}
+            "per_step": per_step, "per_launch_once": once, "steps_per_launch": T,
+            "total": per_step + once / T}
+
+
+def _kernel_source_digest() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2605_19926_amd", "csrc", "jx_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(form: str, digest: str):
+    """HBM bytes per env-step of the headline kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or
+    None when there is none for this form or the kernel source has changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{form}_scale.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256_16") != digest:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_env_step"])
+    except (KeyError, ValueError):
+        return None
 
 
 def _oracle_chunk(args):
@@ -301,10 +335,49 @@ def main() -> int:
     ms = e0.elapsed_time(e1)
     sec = ms / 1e3
     rate = n * K / sec
-    ab = algorithmic_bytes(cfg)
-    per_launch = ab["total"] * n
-    kern_s = sec / K
+    # The fused form runs one kernel per ring chunk (up to 128 steps); the
+    # other forms run one kernel per step.  Layout and state move once per
+    # launch, frames, actions, rewards and dones once per step.
+    chunks = plan(Wu, K)
+    launches = len(chunks) if args.form == "fused" else K
+    ab = algorithmic_bytes(cfg, K // launches)
+    total_bytes = n * (K * ab["per_step"] + launches * ab["per_launch_once"])
+    per_launch = total_bytes / launches
+    bytes_per_env_step = total_bytes / (n * K)
+    kern_s = sec / launches  # average launch duration over the timed region
     achieved = per_launch / kern_s / 1e9
+    tr = measured_traffic(args.form, _kernel_source_digest())
+    traffic = None if tr is None else tr * n * K / launches
+    # write-only ceiling on this machine: a plain fill of the whole frame ring
+    fills = 3
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    obs.fill_(1)
+    f0.record(stream)
+    for _ in range(fills):
+        obs.fill_(0)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    write_ceiling = obs.numel() * fills / (f0.elapsed_time(f1) / 1e3) / 1e9
+    # single-slot variant (every frame to slot 0: the last-level cache can
+    # absorb the frame writes), same form, fewer steps
+    single = None
+    if slots > 1 and args.form in ("fused", "graph"):
+        Ks = min(K, 1024)
+        o0 = obs[:ob]
+        c0 = min(128, Ks)
+        env.rollout(acts[:c0], o0, rew, done, c0, obs_stride=0, graph=args.form == "graph",
+                    fused=args.form == "fused")
+        torch.cuda.synchronize()
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for t in range(0, Ks, 128):
+            c = min(128, Ks - t)
+            env.rollout(acts[t:t + c], o0, rew, done, c, obs_stride=0,
+                        graph=args.form == "graph", fused=args.form == "fused")
+        s1.record(stream)
+        torch.cuda.synchronize()
+        ss = s0.elapsed_time(s1) / 1e3
+        single = {"steps": Ks, "env_steps_per_s": n * Ks / ss, "ms_per_step": ss / Ks * 1e3}
     S = env.get_state()
     line = {
         "metric": "rendered env-steps/s @4096 envs 64x64 RGB; served p50/p99 step latency vs plain",
@@ -324,10 +397,18 @@ def main() -> int:
                    "form": args.form, "launch": launch,
                    "obs_ring_slots": slots, "global_batch": n},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_env_step": ab["total"], "obs_bytes_per_env_step": ab["obs"],
-                     "kernel_avg_us": kern_s * 1e6},
-        "obs_write_gbs": ab["obs"] * n / kern_s / 1e9,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_roll" if args.form == "fused" else
+                               {"persistent": "k_persist", "pipeline": "k_pipe"}.get(args.form, "k_plain"),
+                     "launches": launches, "steps_per_launch": K / launches,
+                     "bytes_per_launch": per_launch,
+                     "bytes_per_env_step": bytes_per_env_step, "obs_bytes_per_env_step": ab["obs"],
+                     "kernel_avg_us": kern_s * 1e6,
+                     "kernel_source_sha256_16": _kernel_source_digest(),
+                     "write_only_ceiling_gbs": write_ceiling,
+                     "frac_of_write_ceiling": achieved / write_ceiling},
+        "single_slot": single,
+        "obs_write_gbs": ab["obs"] * n * K / sec / 1e9,
         "episodes_completed": int(S["episode"].astype(np.int64).sum()),
         "wall_s": wall,
     }

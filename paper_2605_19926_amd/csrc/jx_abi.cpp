@@ -94,6 +94,8 @@ DevCfg derive_cfg(const jx_env_cfg& c) {
   d.r_goal = c.r_goal;
   d.r_key = c.r_key;
   d.tanH = (float)std::tan((double)c.fov_deg * M_PI / 360.0);
+  d.inv_tanH = (float)(1.0 / (double)d.tanH);
+  d.inv_w = (float)(1.0 / (double)c.obs_w);
   return d;
 }
 

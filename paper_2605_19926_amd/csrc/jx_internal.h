@@ -26,7 +26,7 @@ struct DevCfg {
   int32_t max_decor, obs_h, obs_w, n_actions;
   int32_t cap, pad0, pad1, pad2;
   float move, turn, pr2, r_goal;
-  float r_key, tanH, pad3, pad4;
+  float r_key, tanH, inv_tanH, inv_w;  // 1/tanH and 1/obs_w, rounded to float
 };
 static_assert(sizeof(DevCfg) == 80, "DevCfg layout");
 

@@ -71,6 +71,12 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
   return v;
 }
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+__device__ __forceinline__ uint32_t uniform_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ float uniform_f(float v) {
+  return __uint_as_float((uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(v)));
+}
 
 // ---- SplitMix64 (Steele, Lea & Flood 2014) --------------------------------------
 __device__ __forceinline__ uint64_t sm_next(uint64_t& s) {
@@ -277,14 +283,13 @@ struct ColDbg {
 
 // Casts the env's columns and reduces each to a span record in lcol (and
 // writes debug records when asked).
+// sn, cs: sine and cosine of the heading.
 __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int lane, uint8_t* lmap,
-                               uint32_t* lcol, float x, float y, float th, int goal, int door,
-                               int key, uint32_t fl, int nd, int dec0, int dec1) {
+                               uint32_t* lcol, float x, float y, float sn, float cs, int goal,
+                               int door, int key, uint32_t fl, int nd, int dec0, int dec1) {
   const int N = cf.side, H = cf.obs_h, W = cf.obs_w, K = cf.n_colors;
-  if (door >= 0 && !(fl & FL_DOOR_OPEN) && lane == 0) lmap[door] = 2;
-  wave_sync();
-  float sn, cs;
-  sincosf(th, &sn, &cs);
+  // the shut locked door blocks rays like a wall (tile id `shut`, -1 if none)
+  const int shut = (door >= 0 && !(fl & FL_DOOR_OPEN)) ? door : -1;
   const float tanH = cf.tanH;
   const float px = -sn * tanH, py = cs * tanH;
 
@@ -295,33 +300,38 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
   const uint32_t srgb[4] = {kKeyRgb, kGoalRgb, kDecorRgb, kDecorRgb};
   float sY[4], sU[4], sHW[4], sHS[4];
   bool sVis[4];
+  const float halfW = 0.5f * (float)W;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int id = sid[j] < 0 ? 0 : sid[j];
+    sVis[j] = false;
+    sY[j] = sU[j] = sHW[j] = sHS[j] = 0.f;
+    if (sid[j] < 0) continue;  // uniform across the wave
+    const int id = sid[j];
     const float dx = ((float)(id % N) + 0.5f) - x;
     const float dy = ((float)(id / N) + 0.5f) - y;
     const float tY = dx * cs + dy * sn;
     const float tX = dy * cs - dx * sn;
-    const float den = tanH * tY;
+    const float inv = 1.0f / tY;             // one division per sprite
+    const float q = inv * cf.inv_tanH;       // 1 / (tanH tY)
     sY[j] = tY;
-    sVis[j] = sid[j] >= 0 && tY > 0.05f;
-    sU[j] = (0.5f * (float)W) * (1.0f + tX / den);
-    sHW[j] = (0.5f * (float)W) * 0.25f / den;
-    sHS[j] = (float)H * 0.25f / tY;
+    sVis[j] = tY > 0.05f;
+    sU[j] = halfW * (1.0f + tX * q);
+    sHW[j] = halfW * 0.25f * q;
+    sHS[j] = (float)H * 0.25f * inv;
   }
 
   const int ix0 = (int)floorf(x), iy0 = (int)floorf(y);
   const float halfH = (float)(H >> 1);
   const float INF = __builtin_huge_valf();
   for (int col = lane; col < W; col += 64) {
-    const float camX = (float)(2 * col + 1 - W) / (float)W;
+    const float camX = (float)(2 * col + 1 - W) * cf.inv_w;
     const float rx = fmaf(camX, px, cs);
     const float ry = fmaf(camX, py, sn);
     const int ix = ix0, iy = iy0;
     const int stx = rx > 0.f ? 1 : -1, sty = ry > 0.f ? 1 : -1;
     float Xn = (float)(rx > 0.f ? ix + 1 : ix);
     float Yn = (float)(ry > 0.f ? iy + 1 : iy);
-    const float ivx = 1.0f / rx, ivy = 1.0f / ry;
+    const float ivx = __builtin_amdgcn_rcpf(rx), ivy = __builtin_amdgcn_rcpf(ry);
     float tx = rx != 0.f ? (Xn - x) * ivx : INF;
     float ty = ry != 0.f ? (Yn - y) * ivy : INF;
     float tst = INF;
@@ -344,15 +354,15 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
       ty = sx ? ty : nty;
       if ((unsigned)id >= (unsigned)NN) break;
       const int v = lmap[id];
-      if (v) {
+      if (v || id == shut) {
         hit = id;
-        cell = v;
+        cell = id == shut ? 2 : 1;
         break;
       }
     }
     uint32_t wc = (cell == 2) ? kDoor : kPalette[(hit < 0 ? 0 : hit) % K];
     if (side) wc = (wc >> 1) & 0x7F7F7Fu;
-    const float hh = (float)H / (2.0f * tst);
+    const float hh = halfH * __builtin_amdgcn_rcpf(tst);
     const uint32_t wcount = (uint32_t)fminf(fmaxf(ceilf(hh - 0.5f), 0.f), halfH);
     // nearest covering sprite; on equal depth the later slot wins (painted last)
     float bestY = INF, bestHS = 0.f;
@@ -469,22 +479,32 @@ __device__ __forceinline__ void load_env(const DevState& S, int env, int lane, E
   in.seed = S.seed[env];
 }
 
-// Stage, step, reset and column cast of one env from its loaded inputs: LDS
-// and registers only, no global stores (so a wave doing only this never waits
-// on outstanding stores).  All lanes run the uniform parts redundantly.
-// action < 0: read this env's action from io.act.
+// Copies the env's layout words from registers into the wave's LDS map.  The
+// LDS map is read-only afterwards (the shut door is tested separately), so a
+// wave that keeps one env for several steps stages it once.
 template <int MAXN>
-__device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevIo& io, int action,
-                            int lane, uint8_t* lmap, uint32_t* lcol, EnvOut& o) {
-  const DevCfg& cf = in.cf;
-  const int env = in.env;
-  const int N = cf.side, NN = N * N;
+__device__ __forceinline__ void stage_map(const EnvIn<MAXN>& in, int lane, uint8_t* lmap) {
+  const int NN = in.cf.side * in.cf.side;
   uint32_t* lm32 = reinterpret_cast<uint32_t*>(lmap);
 #pragma unroll
   for (int k = 0; k < EnvIn<MAXN>::kMapWords; ++k) {
     const int i = lane + 64 * k;
     if (i < ((NN + 3) >> 2)) lm32[i] = in.map[k];
   }
+}
+
+// Step, reset and column cast of one env from its loaded inputs: LDS and
+// registers only, no global stores (so a wave doing only this never waits on
+// outstanding stores).  All lanes run the uniform parts redundantly.
+// STAGE: copy the layout into LDS first (else it is already there).
+// action < 0: read this env's action from io.act.
+template <int MAXN, bool STAGE = true>
+__device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevIo& io, int action,
+                            int lane, uint8_t* lmap, uint32_t* lcol, EnvOut& o) {
+  const DevCfg& cf = in.cf;
+  const int env = in.env;
+  const int N = cf.side;
+  if (STAGE) stage_map<MAXN>(in, lane, lmap);
   float x = in.x, y = in.y, th = in.th;
   uint32_t t = in.t, ep = in.ep;
   int goal = in.goal, door = in.door, key = in.key;
@@ -498,10 +518,11 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   float reward = 0.f;
   uint32_t ev = 0;
   bool done = false;
+  float sn, cs;
+  sincosf(th, &sn, &cs);
+  bool heading_changed = false;
   if (mode == MODE_STEP) {
     const int a = action >= 0 ? action : io.act[env];
-    float sn, cs;
-    sincosf(th, &sn, &cs);
     float mvx = 0.f, mvy = 0.f, dth = 0.f;
     if (a >= cf.n_actions) {
       ev |= EV_INVALID;
@@ -523,6 +544,7 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
       if (t2 < 0.f) t2 += kTwoPiF;
       else if (t2 >= kTwoPiF) t2 -= kTwoPiF;
       th = t2;
+      heading_changed = true;
     }
     const float mx = cf.move * mvx, my = cf.move * mvy;
     const bool dclosed = door >= 0 && !(fl & FL_DOOR_OPEN);
@@ -577,9 +599,11 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
     ep = e;
     fl = 0;
     if (done) ev |= EV_RESET;
+    heading_changed = true;
   }
+  if (heading_changed) sincosf(th, &sn, &cs);
   if (io.obs || io.dbg)
-    render_columns(cf, io, env, lane, lmap, lcol, x, y, th, goal, door, key, fl, nd, dec0, dec1);
+    render_columns(cf, io, env, lane, lmap, lcol, x, y, sn, cs, goal, door, key, fl, nd, dec0, dec1);
   o.obs_off = S.uniform ? (int64_t)env * S.obs_stride : S.obs_off[env];
   o.env = env;
   o.W = cf.obs_w;
@@ -628,7 +652,7 @@ __device__ void write_back(const DevState& S, const DevIo& io, const EnvOut& o, 
 
 // The whole per-env pipeline in one wave.
 template <int MAXN>
-__device__ void process_env(const DevState& S, const DevIo& io, int env, int lane, uint8_t* lmap,
+__device__ __forceinline__ void process_env(const DevState& S, const DevIo& io, int env, int lane, uint8_t* lmap,
                             uint32_t* lcol) {
   EnvIn<MAXN> in;
   load_env<MAXN>(S, env, lane, in);
@@ -745,8 +769,9 @@ __global__ __launch_bounds__(64 * WPB) void k_serve(const DevState* states, cons
   queue_drain(v, lane, [&](int pos) {
     const int d = __builtin_amdgcn_readfirstlane(items[pos].desc);
     const int env = __builtin_amdgcn_readfirstlane(items[pos].env);
-    const DevState S = states[d];
-    const DevIo io = ios[d];
+    // fields are read from the descriptors where they are used (scalar loads)
+    const DevState& S = states[d];
+    const DevIo& io = ios[d];
     process_env<kMaxSide>(S, io, env, lane, smap[w], scol[w]);
   });
 }
@@ -801,8 +826,8 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
 }
 
 // Fused rollout: each wave carries its env through all T steps of a rollout
-// with the state in registers and the map words in registers (restaged into
-// LDS every step), after loading the env's T actions up front.  Inside the
+// with the state in registers and its layout staged once in LDS, loading the
+// env's actions 128 steps at a time.  Inside the
 // step loop the wave issues no global loads, so its frame stores never stall
 // it, and waves drift out of phase: one wave's casting overlaps another's
 // stores.  Waves take envs by a static stride over the work order.  Per step
@@ -825,8 +850,8 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
     const int env = __builtin_amdgcn_readfirstlane(S.order[item]);
     EnvIn<MAXN> in;
     load_env<MAXN>(S, env, lane, in);
-    uint32_t n_invalid = 0;
-    EnvOut o;
+    stage_map<MAXN>(in, lane, smap[w]);
+    uint32_t n_invalid = 0, last_ev = 0;
     for (int t0 = 0; t0 < T; t0 += 128) {
       // lane l holds the actions of steps t0 + l and t0 + 64 + l
       const int s0 = t0 + lane, s1 = t0 + 64 + lane;
@@ -835,42 +860,50 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
       const int tend = T - t0 < 128 ? T - t0 : 128;
       for (int k = 0; k < tend; ++k) {
         const int a = __shfl((int)(k < 64 ? a0 : a1), k & 63, 64);
-        produce_env<MAXN>(in, S, io, a, lane, smap[w], scol[w], o);
+        // an opaque copy of the lane id keeps the per-column set-up inside the
+        // loop instead of hoisted out of it and held live across all steps
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        EnvOut o;
+        produce_env<MAXN, false>(in, S, io, a, ln, smap[w], scol[w], o);
         const int t = t0 + k;
-        fill_frame(scol[w], obs + (int64_t)t * obs_stride + o.obs_off, o.W, o.H, lane, store_mode);
+        fill_frame(scol[w], obs + (int64_t)t * obs_stride + o.obs_off, o.W, o.H, ln, store_mode);
         if (lane == 0) {
           rew[(int64_t)t * n + env] = o.reward;
           dn[(int64_t)t * n + env] = (uint8_t)o.done;
         }
-        n_invalid += (o.ev & EV_INVALID) ? 1u : 0u;
-        in.x = o.x;
-        in.y = o.y;
-        in.th = o.th;
-        in.t = o.t;
-        in.ep = o.ep;
-        in.fl = o.fl;
-        in.nd = (int)o.nd;
-        in.goal = o.goal;
-        in.door = o.door;
-        in.key = o.key;
-        in.dec0 = o.dec0;
-        in.dec1 = o.dec1;
+        // the carried state is uniform across the wave: keep it in scalar registers
+        const uint32_t ev = uniform_u(o.ev);
+        n_invalid += (ev & EV_INVALID) ? 1u : 0u;
+        last_ev = ev;
+        in.x = uniform_f(o.x);
+        in.y = uniform_f(o.y);
+        in.th = uniform_f(o.th);
+        in.t = uniform_u(o.t);
+        in.ep = uniform_u(o.ep);
+        in.fl = uniform_u(o.fl);
+        in.nd = (int)uniform_u(o.nd);
+        in.goal = (int)uniform_u((uint32_t)o.goal);
+        in.door = (int)uniform_u((uint32_t)o.door);
+        in.key = (int)uniform_u((uint32_t)o.key);
+        in.dec0 = (int)uniform_u((uint32_t)o.dec0);
+        in.dec1 = (int)uniform_u((uint32_t)o.dec1);
       }
     }
     if (lane == 0 && T > 0) {
-      S.x[env] = o.x;
-      S.y[env] = o.y;
-      S.th[env] = o.th;
-      S.t[env] = o.t;
-      S.ep[env] = o.ep;
-      S.goal[env] = o.goal;
-      S.door[env] = o.door;
-      S.key[env] = o.key;
-      S.decor[2 * env] = o.dec0;
-      S.decor[2 * env + 1] = o.dec1;
-      S.flags[env] = (uint8_t)o.fl;
-      S.ndecor[env] = (uint8_t)o.nd;
-      S.events[env] = (uint8_t)o.ev;
+      S.x[env] = in.x;
+      S.y[env] = in.y;
+      S.th[env] = in.th;
+      S.t[env] = in.t;
+      S.ep[env] = in.ep;
+      S.goal[env] = in.goal;
+      S.door[env] = in.door;
+      S.key[env] = in.key;
+      S.decor[2 * env] = in.dec0;
+      S.decor[2 * env + 1] = in.dec1;
+      S.flags[env] = (uint8_t)in.fl;
+      S.ndecor[env] = (uint8_t)in.nd;
+      S.events[env] = (uint8_t)last_ev;
       if (n_invalid) S.invalid[env] += n_invalid;
     }
   }

@@ -148,6 +148,26 @@ def _ptr(t) -> int | None:
     return t.data_ptr()
 
 
+def _nbytes(t) -> int:
+    if isinstance(t, np.ndarray):
+        return int(t.nbytes)
+    return int(t.numel()) * int(t.element_size())
+
+
+def _need(name: str, t, nbytes: int, device=None) -> None:
+    """Host-side size (and device) check of a buffer the kernels will touch:
+    the C-ABI takes raw pointers and cannot see extents."""
+    if t is None:
+        raise JxError(JX_EINVAL, f"{name} is required")
+    if not t.is_contiguous():
+        raise JxError(JX_EINVAL, f"{name} must be contiguous")
+    if device is not None and t.device != device:
+        raise JxError(JX_EINVAL, f"{name} is on {t.device}, expected {device}")
+    have = _nbytes(t)
+    if have < nbytes:
+        raise JxError(JX_EINVAL, f"{name} holds {have} bytes, {nbytes} needed")
+
+
 def make_layout(seed: int, cfg: dict) -> np.ndarray:
     """Host-only maze generator of the library (no device needed)."""
     c = make_cfg(cfg)
@@ -198,6 +218,11 @@ class Env:
     # -- lifecycle ---------------------------------------------------------------
     def reset(self, obs=None):
         torch = self.torch
+        if obs is not None:
+            per_cfg = [c["obs_h"] * c["obs_w"] * 3 for c in self.cfgs]
+            need = (per_cfg[0] * self.n if self.cfg_index is None
+                    else int(sum(per_cfg[i] for i in self.cfg_index)))
+            _need("obs", obs, need, self.dev)
         check(lib().jx_reset(self.ctx, self.n, _ptr(self.seeds), self._carr, len(self.cfgs),
                              _ptr(self.cfg_index), _ptr(obs)))
         self.obs_bytes = int(lib().jx_obs_bytes(self.ctx))
@@ -224,19 +249,36 @@ class Env:
         return self.torch.empty(slots * self.obs_bytes, dtype=torch_uint8(self.torch),
                                 device=self.dev)
 
+    def _check_frame(self, obs, name="obs"):
+        if obs is not None and self._reset_done:
+            _need(name, obs, self.obs_bytes, self.dev)
+
     def step(self, actions, obs, reward=None, done=None):
         reward = self.reward if reward is None else reward
         done = self.done if done is None else done
+        _need("actions", actions, self.n, self.dev)
+        _need("reward", reward, 4 * self.n, self.dev)
+        _need("done", done, self.n, self.dev)
+        self._check_frame(obs)
         check(lib().jx_step(self.ctx, _ptr(actions), _ptr(obs), _ptr(reward), _ptr(done)))
         return reward, done
 
     def rollout(self, actions, obs, reward, done, T: int, obs_stride: int = 0, graph: bool = True,
                 fused: bool = False):
         flags = (JX_ROLLOUT_GRAPH if graph else 0) | (JX_ROLLOUT_FUSED if fused else 0)
+        if T > 0:
+            _need("actions", actions, T * self.n, self.dev)
+            _need("reward", reward, 4 * T * self.n, self.dev)
+            _need("done", done, T * self.n, self.dev)
+            if obs_stride and obs_stride < self.obs_bytes:
+                raise JxError(JX_EINVAL, f"obs_stride {obs_stride} < frame bytes {self.obs_bytes}")
+            if obs is not None:
+                _need("obs", obs, (T - 1) * obs_stride + self.obs_bytes, self.dev)
         check(lib().jx_rollout(self.ctx, T, _ptr(actions), _ptr(obs), obs_stride, _ptr(reward),
                                _ptr(done), flags))
 
     def render(self, obs=None, debug=None):
+        self._check_frame(obs)
         check(lib().jx_render(self.ctx, _ptr(obs), _ptr(debug)))
 
     def sync(self):

@@ -96,3 +96,18 @@ def test_null_arguments_are_errors(jx):
     assert L.jx_server_submit(None, 0, None, None) == jx.JX_EINVAL
     assert L.jx_num_envs(None) == -1
     assert L.jx_obs_bytes(None) == -1
+
+
+def test_binding_checks_buffer_extents():
+    """The binding refuses buffers smaller than a launch touches (the C-ABI
+    sees raw pointers only)."""
+    import torch
+    from paper_2605_19926_amd import jx
+    t = torch.zeros(100, dtype=torch.float32)
+    jx._need("reward", t, 400)
+    with pytest.raises(jx.JxError):
+        jx._need("reward", t, 401)
+    with pytest.raises(jx.JxError):
+        jx._need("reward", t[::2], 10)
+    with pytest.raises(jx.JxError):
+        jx._need("reward", None, 1)

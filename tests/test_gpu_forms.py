@@ -212,6 +212,21 @@ def test_edge_cases():
     buf = torch.zeros(4 * 64 * 64 * 3 + 8, dtype=torch.uint8, device="cuda")
     with pytest.raises(jx.JxError):
         e.step(torch.zeros(4, dtype=torch.uint8, device="cuda"), buf[1:])
+    # buffers too small for the launch are refused before anything is enqueued
+    a8 = torch.zeros(8 * 4, dtype=torch.uint8, device="cuda")
+    r8 = torch.zeros(8 * 4, device="cuda")
+    d8 = torch.zeros(8 * 4, dtype=torch.uint8, device="cuda")
+    frames = torch.zeros(8 * e.obs_bytes, dtype=torch.uint8, device="cuda")
+    with pytest.raises(jx.JxError):
+        e.rollout(a8[:-1], frames, r8, d8, 8, obs_stride=e.obs_bytes)
+    with pytest.raises(jx.JxError):
+        e.rollout(a8, frames[:-1], r8, d8, 8, obs_stride=e.obs_bytes)
+    with pytest.raises(jx.JxError):
+        e.rollout(a8, frames, r8[:-1], d8, 8, obs_stride=e.obs_bytes, fused=True, graph=False)
+    with pytest.raises(jx.JxError):
+        e.step(a8[:3], frames)
+    with pytest.raises(jx.JxError):
+        e.step(a8[:4], frames[:e.obs_bytes - 1])
     # out-of-range state values are refused on the host
     S = e.get_state()
     bad = {"goal": np.array([64, 0, 0, 0], np.int32)}
