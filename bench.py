@@ -241,8 +241,8 @@ def serve_form(jx, n_requests: int, mode: int, n_streams: int = 4) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10_000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=10_240)
+    ap.add_argument("--warmup", type=int, default=128)
     ap.add_argument("--form", choices=["fused", "graph", "eager", "persistent", "pipeline"],
                     default="fused")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0: the form's default)")

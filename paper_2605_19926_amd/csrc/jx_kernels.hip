@@ -248,6 +248,9 @@ __device__ __forceinline__ ColGroup col_group(const uint32_t* lcol, int cq) {
   return g;
 }
 
+// Crossings per batch of the DDA walk (one LDS round trip each).
+constexpr int kDdaBatch = 4;
+
 constexpr uint32_t kCeil3[3] = {kCeil | (kCeil << 24), (kCeil >> 8) | (kCeil << 16),
                                 (kCeil >> 16) | (kCeil << 8)};
 constexpr uint32_t kFloor3[3] = {kFloor | (kFloor << 24), (kFloor >> 8) | (kFloor << 16),
@@ -329,35 +332,66 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
     const float ry = fmaf(camX, py, sn);
     const int ix = ix0, iy = iy0;
     const int stx = rx > 0.f ? 1 : -1, sty = ry > 0.f ? 1 : -1;
-    float Xn = (float)(rx > 0.f ? ix + 1 : ix);
-    float Yn = (float)(ry > 0.f ? iy + 1 : iy);
+    const float Xn = (float)(rx > 0.f ? ix + 1 : ix);
+    const float Yn = (float)(ry > 0.f ? iy + 1 : iy);
     const float ivx = __builtin_amdgcn_rcpf(rx), ivy = __builtin_amdgcn_rcpf(ry);
+    // ray parameter of the next x / y grid line, and its step per line
     float tx = rx != 0.f ? (Xn - x) * ivx : INF;
     float ty = ry != 0.f ? (Yn - y) * ivy : INF;
+    const float dtx = rx != 0.f ? fabsf(ivx) : 0.f, dty = ry != 0.f ? fabsf(ivy) : 0.f;
     float tst = INF;
     int side = 0, hit = -1, cell = 1;
-    // Branch-free walk: every lane crosses one grid line per iteration.  The
-    // tile index moves by +-1 (x crossing) or +-N (y crossing); the border of
-    // blocking tiles (checked on the host) stops every walk inside the map.
-    const float fsx = (float)stx, fsy = (float)sty;
+    // Branch-free walk in batches: the sequence of tiles a ray crosses does
+    // not depend on the map, only where it stops does.  Each batch computes
+    // the next kDdaBatch crossings (one grid line each: the tile index moves
+    // by +-1 on an x crossing, +-N on a y crossing, and that axis's line
+    // parameter advances by its spacing |1/r|; over at most 4N+8 crossings the
+    // accumulated rounding stays a few ulp), issues their LDS reads
+    // together and keeps the first blocking one, so a lane waits for one LDS
+    // round trip per batch instead of one per crossing.  The border of
+    // blocking tiles (checked on the host) stops every walk inside the map;
+    // crossings past the stop are discarded and read a clamped address.
     const int dy = sty * N, NN = N * N;
     int id = iy * N + ix;
-    for (int it = 0; it < 4 * N + 8; ++it) {
-      const bool sx = tx < ty;
-      tst = sx ? tx : ty;
-      side = sx ? 0 : 1;
-      id += sx ? stx : dy;
-      Xn += sx ? fsx : 0.f;
-      Yn += sx ? 0.f : fsy;
-      const float ntx = (Xn - x) * ivx, nty = (Yn - y) * ivy;
-      tx = sx ? ntx : tx;
-      ty = sx ? ty : nty;
-      if ((unsigned)id >= (unsigned)NN) break;
-      const int v = lmap[id];
-      if (v || id == shut) {
-        hit = id;
-        cell = id == shut ? 2 : 1;
-        break;
+    const uint32_t last = (uint32_t)(NN - 1);
+    bool found = false;
+    for (int it = 0; it < 4 * N + 8 && !found; it += kDdaBatch) {
+      int ids[kDdaBatch];
+      float ts[kDdaBatch];
+      bool sd[kDdaBatch];
+#pragma unroll
+      for (int u = 0; u < kDdaBatch; ++u) {
+        const bool sx = tx < ty;
+        ts[u] = sx ? tx : ty;
+        sd[u] = !sx;
+        id += sx ? stx : dy;
+        tx = sx ? tx + dtx : tx;
+        ty = sx ? ty : ty + dty;
+        ids[u] = id;
+      }
+      // bit u: crossing u stops the walk (blocking tile, shut door, or off the map)
+      uint32_t stop = 0;
+#pragma unroll
+      for (int u = 0; u < kDdaBatch; ++u) {
+        const uint32_t uid = (uint32_t)ids[u];
+        const uint32_t v = lmap[uid < last ? uid : last];
+        stop |= (uint32_t)((v != 0u) | (ids[u] == shut) | (uid > last)) << u;
+      }
+      tst = ts[kDdaBatch - 1];  // kept only if nothing in the batch stops the walk
+      side = sd[kDdaBatch - 1] ? 1 : 0;
+      if (stop) {
+        int sid_ = ids[kDdaBatch - 1];
+#pragma unroll
+        for (int u = kDdaBatch - 2; u >= 0; --u) {  // the earliest stop wins
+          const bool b = (stop >> u) & 1u;
+          tst = b ? ts[u] : tst;
+          side = b ? (sd[u] ? 1 : 0) : side;
+          sid_ = b ? ids[u] : sid_;
+        }
+        found = true;
+        const bool out = (uint32_t)sid_ > last;
+        hit = out ? -1 : sid_;
+        cell = (!out && sid_ == shut) ? 2 : 1;
       }
     }
     uint32_t wc = (cell == 2) ? kDoor : kPalette[(hit < 0 ? 0 : hit) % K];

@@ -37,7 +37,7 @@ def env_cfg(**kw) -> dict:
 # The five workloads: (number used to derive seeds, env count, steps, cfg).
 TINY = dict(number=1, name="tiny-16env-8x8-64px", n_envs=16, steps=1000,
             cfg=env_cfg(side=8, n_colors=4, loop_frac=0.0, n_actions=4, episode_cap=256))
-SCALE = dict(number=2, name="scale-4096env-16x16-64px", n_envs=4096, steps=10_000, warmup=100,
+SCALE = dict(number=2, name="scale-4096env-16x16-64px", n_envs=4096, steps=10_240, warmup=128,
              cfg=env_cfg(side=16, n_colors=8, loop_frac=0.1, goal_sprite=1, n_actions=6,
                          episode_cap=512))
 KEYDOOR = dict(number=3, name="keydoor-8192env-32x32-84px", n_envs=8192, steps=2048,
