@@ -223,28 +223,58 @@ __device__ __forceinline__ void store12(uint8_t* p, uint32_t a, uint32_t b, uint
   }
 }
 
-// Pixel colours of one column group (4 columns) at distance index i from the
-// horizon: sprite band, else wall band, else background.  Branch-free.
+// Pixel colours of one column group (4 columns), byte-parallel.  A column's
+// span record is (wall rgb | cov << 24, sprite rgb | sc << 24), where rows at
+// distance i < sc from the horizon show the sprite, sc <= i < cov the wall and
+// the rest ceiling (above) or floor (below).  The group keeps:
+//   pw, ps  the 4 wall / sprite colours packed as 12 frame bytes (3 dwords);
+//   cova/covb, sca/scb  cov and sc of pixels (0,1) / (2,3) in bytes 1 and 3,
+//           biased by 0x7F, so that subtracting i from both bytes at once
+//           leaves the byte's sign bit set exactly when i < count (0x7F + count
+//           - i stays in [0x40, 0xBF] for counts and i up to 64: no carries);
+//   any     the largest cov: rows at i >= any are background in this group.
 struct ColGroup {
-  uint32_t fgS[4], fgW[4], sc[4], cov[4];
-  uint32_t any;  // rows at distance < any hold a wall or sprite pixel in this group
+  uint32_t pw[3], ps[3];
+  uint32_t cova, covb, sca, scb;
+  uint32_t any;
 };
+
+// v_perm_b32 selectors: bytes 0-3 of {hi, lo} come from lo, 4-7 from hi;
+// 8..11 replicate the sign bit of bytes 1, 3, 5, 7; 12 gives 0x00.
+constexpr uint32_t kSelPack0 = 0x04020100u;  // lo.b0 lo.b1 lo.b2 hi.b0
+constexpr uint32_t kSelPack1 = 0x05040201u;  // lo.b1 lo.b2 hi.b0 hi.b1
+constexpr uint32_t kSelPack2 = 0x06050402u;  // lo.b2 hi.b0 hi.b1 hi.b2
+constexpr uint32_t kSelCount = 0x070C030Cu;  // 0, lo.b3, 0, hi.b3
+constexpr uint32_t kSelMask0 = 0x09080808u;  // pixel 0 x3, pixel 1
+constexpr uint32_t kSelMask1 = 0x0A0A0909u;  // pixel 1 x2, pixel 2 x2
+constexpr uint32_t kSelMask2 = 0x0B0B0B0Au;  // pixel 2, pixel 3 x3
+constexpr uint32_t kCountBias = 0x7F007F00u;
+constexpr uint32_t kRowStep = 0x01000100u;    // i in bytes 1 and 3
+
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+__device__ __forceinline__ uint32_t bitsel(uint32_t m, uint32_t a, uint32_t b) {
+  return (m & a) | (~m & b);
+}
+
 __device__ __forceinline__ ColGroup col_group(const uint32_t* lcol, int cq) {
   const uint4* l4 = reinterpret_cast<const uint4*>(lcol);
   const uint4 A = l4[2 * cq], B = l4[2 * cq + 1];
-  const uint32_t w[4] = {A.x, A.z, B.x, B.z}, sp[4] = {A.y, A.w, B.y, B.w};
+  // A = (w0, s0, w1, s1), B = (w2, s2, w3, s3)
   ColGroup g;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t wc = w[k] >> 24, scn = sp[k] >> 24;
-    g.fgS[k] = sp[k] & 0xFFFFFFu;
-    g.fgW[k] = w[k] & 0xFFFFFFu;
-    g.sc[k] = scn;
-    g.cov[k] = wc > scn ? wc : scn;
-  }
-  const uint32_t a = g.cov[0] > g.cov[1] ? g.cov[0] : g.cov[1];
-  const uint32_t b = g.cov[2] > g.cov[3] ? g.cov[2] : g.cov[3];
-  g.any = a > b ? a : b;
+  g.pw[0] = perm(A.z, A.x, kSelPack0);
+  g.pw[1] = perm(B.x, A.z, kSelPack1);
+  g.pw[2] = perm(B.z, B.x, kSelPack2);
+  g.ps[0] = perm(A.w, A.y, kSelPack0);
+  g.ps[1] = perm(B.y, A.w, kSelPack1);
+  g.ps[2] = perm(B.w, B.y, kSelPack2);
+  g.cova = perm(A.z, A.x, kSelCount) + kCountBias;
+  g.covb = perm(B.z, B.x, kSelCount) + kCountBias;
+  g.sca = perm(A.w, A.y, kSelCount) + kCountBias;
+  g.scb = perm(B.w, B.y, kSelCount) + kCountBias;
+  const uint32_t a = max(A.x >> 24, A.z >> 24), b = max(B.x >> 24, B.z >> 24);
+  g.any = max(a, b);
   return g;
 }
 
@@ -256,26 +286,24 @@ constexpr uint32_t kCeil3[3] = {kCeil | (kCeil << 24), (kCeil >> 8) | (kCeil << 
 constexpr uint32_t kFloor3[3] = {kFloor | (kFloor << 24), (kFloor >> 8) | (kFloor << 16),
                                  (kFloor >> 16) | (kFloor << 8)};
 
-// Writes the mirrored row pair at distance i (row H/2-1-i above, H/2+i below).
-// When no lane of the wave has a wall or sprite pixel at its distance, the
-// whole wave stores the constant ceiling and floor patterns.
-__device__ __forceinline__ void emit_pair(const ColGroup& g, uint32_t i, uint8_t* up, uint8_t* dn,
-                                          int nt) {
+// Writes the mirrored row pair at distance i (row H/2-1-i above, H/2+i below);
+// ii = i * kRowStep.  When no lane of the wave has a wall or sprite pixel at
+// its distance, the whole wave stores the constant ceiling and floor patterns.
+__device__ __forceinline__ void emit_pair(const ColGroup& g, uint32_t i, uint32_t ii, uint8_t* up,
+                                          uint8_t* dn, int nt) {
   if (__ballot(i < g.any) == 0ull) {
     store12(up, kCeil3[0], kCeil3[1], kCeil3[2], nt);
     store12(dn, kFloor3[0], kFloor3[1], kFloor3[2], nt);
     return;
   }
-  uint32_t pu[4], pd[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint32_t fg = i < g.sc[k] ? g.fgS[k] : g.fgW[k];
-    const bool c = i < g.cov[k];
-    pu[k] = c ? fg : kCeil;
-    pd[k] = c ? fg : kFloor;
-  }
-  store12(up, pu[0] | (pu[1] << 24), (pu[1] >> 8) | (pu[2] << 16), (pu[2] >> 16) | (pu[3] << 8), nt);
-  store12(dn, pd[0] | (pd[1] << 24), (pd[1] >> 8) | (pd[2] << 16), (pd[2] >> 16) | (pd[3] << 8), nt);
+  const uint32_t ca = g.cova - ii, cb = g.covb - ii;  // sign bits: i < cov
+  const uint32_t sa = g.sca - ii, sb = g.scb - ii;    // sign bits: i < sc
+  const uint32_t m0 = perm(cb, ca, kSelMask0), m1 = perm(cb, ca, kSelMask1), m2 = perm(cb, ca, kSelMask2);
+  const uint32_t x0 = bitsel(perm(sb, sa, kSelMask0), g.ps[0], g.pw[0]);
+  const uint32_t x1 = bitsel(perm(sb, sa, kSelMask1), g.ps[1], g.pw[1]);
+  const uint32_t x2 = bitsel(perm(sb, sa, kSelMask2), g.ps[2], g.pw[2]);
+  store12(up, bitsel(m0, x0, kCeil3[0]), bitsel(m1, x1, kCeil3[1]), bitsel(m2, x2, kCeil3[2]), nt);
+  store12(dn, bitsel(m0, x0, kFloor3[0]), bitsel(m1, x1, kFloor3[1]), bitsel(m2, x2, kFloor3[2]), nt);
 }
 
 struct ColDbg {
@@ -412,12 +440,14 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
         any = true;
       }
     }
-    uint32_t srec = 0u;
+    uint32_t srec = 0u, scount = 0u;
     if (any) {
-      const uint32_t scount = (uint32_t)fminf(fmaxf(ceilf(bestHS - 0.5f), 0.f), halfH);
+      scount = (uint32_t)fminf(fmaxf(ceilf(bestHS - 0.5f), 0.f), halfH);
       srec = bestRgb | (scount << 24);
     }
-    lcol[2 * col] = wc | (wcount << 24);
+    // span record: wall colour with the covered half-height (wall or sprite),
+    // sprite colour with the sprite's half-height
+    lcol[2 * col] = wc | ((wcount > scount ? wcount : scount) << 24);
     lcol[2 * col + 1] = srec;
     if (io.dbg) {
       ColDbg* d = reinterpret_cast<ColDbg*>(io.dbg) + (int64_t)env * io.dbg_stride + col;
@@ -441,8 +471,11 @@ __device__ void fill_frame(const uint32_t* lcol, uint8_t* base, int W, int H, in
       uint8_t* up = base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq;
       uint8_t* dn = base + (int64_t)(H2 + i) * rowb + 12 * cq;
       const int64_t step = (int64_t)di * rowb;
+      uint32_t ii = (uint32_t)i * kRowStep;
+      const uint32_t dii = (uint32_t)di * kRowStep;
       for (; i < H2; i += di) {
-        emit_pair(g, (uint32_t)i, up, dn, nt);
+        emit_pair(g, (uint32_t)i, ii, up, dn, nt);
+        ii += dii;
         up -= step;
         dn += step;
       }
@@ -450,7 +483,7 @@ __device__ void fill_frame(const uint32_t* lcol, uint8_t* base, int W, int H, in
   } else {
     for (int k = lane; k < G2; k += 64) {
       const ColGroup g = col_group(lcol, cq);
-      emit_pair(g, (uint32_t)i, base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq,
+      emit_pair(g, (uint32_t)i, (uint32_t)i * kRowStep, base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq,
                 base + (int64_t)(H2 + i) * rowb + 12 * cq, nt);
       i += di;
       cq += dq;
