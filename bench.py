@@ -31,6 +31,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 RING = 128
 
 
+def progress(msg: str) -> None:
+    """One progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes(cfg: dict, steps_per_launch: int = 1) -> dict:
     """HBM bytes one env must move at minimum, per env-step, when one launch
     advances it `steps_per_launch` steps.  Frames, actions, rewards and done
@@ -168,40 +173,61 @@ def batch_form(jx, torch, launches: list[dict], rollouts: int = 2) -> dict:
     return out
 
 
-def serve_form(jx, n_requests: int, mode: int, n_streams: int = 4) -> dict:
-    """Serving workload: Poisson arrivals (2000 req/s) over 256 client slots,
-    clients of 1-512 envs (log-uniform), side 8-64, frames 64 or 84 square.  An
-    arrival thread submits each request at its time; a collector waits for every
-    ticket (frames, rewards, dones copied to host).  Latency is submit-to-ready
-    as measured by the server."""
+def serve_form(jx, n_requests: int, mode: int, rate: float = W.SERVE["rate"],
+               budget: int = int(64e9), n_streams: int = 4) -> dict:
+    """Serving workload: Poisson arrivals over 256 client slots, clients of
+    1-512 envs (log-uniform), side 8-64, frames 64 or 84 square.  Every client is
+    opened before the clock starts (with a tight budget most of them queue for
+    admission); an arrival thread submits each request at its trace time and
+    closes a client right after its last request; four collector threads take
+    completed requests in completion order and copy their frames, rewards and
+    dones to host memory.  Latency is submit-to-ready as measured by the
+    server."""
     import threading
-    import queue as q_
-    tr = W.serve_trace(n_requests)
-    srv = jx.Server(hbm_budget=int(64e9), n_streams=n_streams, mode=mode)
+    tr = W.serve_trace(n_requests, rate=rate)
+    srv = jx.Server(hbm_budget=budget, n_streams=n_streams, mode=mode)
     sessions = {}
     last_of = {}
     for k, sid in enumerate(tr["session"]):
         last_of[int(sid)] = k
-    work: "q_.Queue" = q_.Queue()
     lat = []
     env_steps = [0]
     t_done = [0.0]
+    failure = []
+
+    left = [n_requests]
+    lock = threading.Lock()
+    max_n = int(tr["n_envs"].max())
+    max_fb = int(tr["obs"].max()) ** 2 * 3
 
     def collector():
+        # collects requests in completion order (as independent clients would),
+        # copying each one's frames, rewards and dones into this thread's host
+        # buffers (allocated once, at the largest client's size)
+        mine = (np.empty(max_n * max_fb, np.uint8), np.empty(max_n, np.float32),
+                np.empty(max_n, np.uint8))
+        deadline = time.perf_counter() + 600.0
         while True:
-            item = work.get()
-            if item is None:
-                return
-            cid, tk, close = item
-            res = srv.wait(cid, tk, want_obs=True)
-            lat.append(res[3])
-            env_steps[0] += res[1].shape[0]
-            t_done[0] = time.perf_counter()
-            if close:
-                srv.close_client(cid)
+            with lock:
+                if left[0] == 0 or failure:
+                    return
+                left[0] -= 1
+            got = None
+            while got is None:
+                if time.perf_counter() > deadline:
+                    failure.append("serving run did not complete within 600 s")
+                    return
+                got = srv.wait_any(timeout=1.0)
+            cid, tk = got
+            n, fb = srv.sizes[cid]
+            out = (mine[0][:n * fb], mine[1][:n], mine[2][:n])
+            res = srv.wait(cid, tk, out=out)
+            with lock:
+                lat.append(res[3])
+                env_steps[0] += res[1].shape[0]
+                t_done[0] = max(t_done[0], time.perf_counter())
 
-    # clients are opened (mazes generated, episode 0 reset on the device) before
-    # the clock starts; requests then arrive on the trace's schedule
+    queued = 0
     for k in range(n_requests):
         sid = int(tr["session"][k])
         if sid not in sessions:
@@ -210,32 +236,55 @@ def serve_form(jx, n_requests: int, mode: int, n_streams: int = 4) -> dict:
             ob = int(tr["obs"][sid])
             cfg = W.env_cfg(side=side, loop_frac=0.1, goal_sprite=1, obs_h=ob, obs_w=ob)
             seeds = tr["seed_base"][sid] + np.arange(n, dtype=np.uint64)
-            cid, _ = srv.open(seeds, cfg)
+            cid, admitted = srv.open(seeds, cfg)
+            queued += 0 if admitted else 1
             sessions[sid] = (cid, n)
-    th = threading.Thread(target=collector)
-    th.start()
+    # everything the arrival loop needs is prepared before the clock
     rng = np.random.default_rng(11)
-    t0 = time.perf_counter()
+    plan = []
     for k in range(n_requests):
         sid = int(tr["session"][k])
         cid, n = sessions[sid]
-        wait = t0 + float(tr["t"][k]) - time.perf_counter()
-        if wait > 0:
-            time.sleep(wait)
-        tk = srv.submit(cid, rng.integers(0, 6, size=n, dtype=np.uint8))
-        work.put((cid, tk, last_of[sid] == k))
-    work.put(None)
-    th.join()
+        plan.append((float(tr["t"][k]), cid, rng.integers(0, 6, size=n, dtype=np.uint8),
+                     last_of[sid] == k))
+    ths = [threading.Thread(target=collector) for _ in range(4)]
+    old_switch = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)   # the threads hand the interpreter over often
+    for th in ths:
+        th.start()
+    t0 = time.perf_counter()
+    for t_arr, cid, acts, last in plan:
+        while True:  # sleep for long gaps, spin for short ones
+            wait = t0 + t_arr - time.perf_counter()
+            if wait <= 0:
+                break
+            if wait > 3e-4:
+                time.sleep(wait - 2e-4)
+        srv.submit(cid, acts)
+        if last:
+            srv.close_client(cid)
+    t_submitted = time.perf_counter() - t0
+    for th in ths:
+        th.join()
+    sys.setswitchinterval(old_switch)
+    if failure:
+        raise RuntimeError(failure[0])
+    progress(f"serving {'coalesced' if mode == jx.JX_SERVE_COALESCE else 'plain'} "
+             f"rate {rate:g}/s budget {budget} done")
     wall = t_done[0] - t0
     st = srv.stats()
     srv.close()
     lat_ms = np.array(lat) * 1e3
     return {"mode": "coalesced" if mode == jx.JX_SERVE_COALESCE else "plain-per-request",
             "streams": n_streams if mode == jx.JX_SERVE_COALESCE else 1,
-            "requests": n_requests, "p50_ms": float(np.percentile(lat_ms, 50)),
+            "offered_req_per_s": rate, "submitted_req_per_s": n_requests / t_submitted,
+            "hbm_budget_bytes": budget,
+            "requests": n_requests, "clients": len(sessions),
+            "clients_queued_for_admission": queued,
+            "p50_ms": float(np.percentile(lat_ms, 50)),
             "p99_ms": float(np.percentile(lat_ms, 99)), "mean_ms": float(lat_ms.mean()),
             "env_steps_per_s": env_steps[0] / wall, "launches": int(st["launches"]),
-            "offered_req_per_s": W.SERVE["rate"], "wall_s": wall}
+            "wall_s": wall}
 
 
 def main() -> int:
@@ -251,7 +300,7 @@ def main() -> int:
     ap.add_argument("--single-slot", action="store_true", help="write every frame to one slot")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batching and serving forms")
-    ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-requests", type=int, default=20_000)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 launches), to scale "
@@ -413,15 +462,24 @@ def main() -> int:
         "wall_s": wall,
     }
     env.close()
+    progress(f"headline {args.form}: {rate:.4g} env-steps/s")
     if not args.no_forms:
         line["batching_form"] = batch_form(jx, torch, [
             {"form": 0, "waves_per_group": 4, "groups_per_cu": 1, "store_mode": 0, "fused": True},
             {"form": 0, "waves_per_group": 4, "groups_per_cu": 1, "store_mode": 0},
             {"form": 1, "waves_per_group": 2, "groups_per_cu": 4, "store_mode": 0},
             {"form": 2, "waves_per_group": 2, "groups_per_cu": 2, "store_mode": 0}])
-        line["serving_form"] = [serve_form(jx, args.serve_requests, jx.JX_SERVE_COALESCE),
-                                serve_form(jx, args.serve_requests, jx.JX_SERVE_PLAIN)]
+        progress("batching form done")
+        nr = args.serve_requests
+        line["serving_form"] = {
+            "workload": W.SERVE["name"],
+            "runs": [serve_form(jx, nr, jx.JX_SERVE_COALESCE),
+                     serve_form(jx, nr, jx.JX_SERVE_PLAIN),
+                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, rate=8 * W.SERVE["rate"]),
+                     serve_form(jx, nr, jx.JX_SERVE_PLAIN, rate=8 * W.SERVE["rate"]),
+                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, budget=256 << 20)]}
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle on the host cores)")
         line["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(line), flush=True)
     return 0

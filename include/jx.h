@@ -230,7 +230,20 @@ jx_status jx_server_submit(jx_server* srv, int32_t client, const uint8_t* action
 jx_status jx_server_wait(jx_server* srv, uint64_t ticket, double timeout_s, uint8_t* obs_host,
                          float* reward_host, uint8_t* done_host, double* latency_s);
 
-/* Releases the client once its queued requests have completed. */
+/* Completion queue: waits (timeout_s < 0: forever; 0: poll, JX_EBUSY if none)
+ * for a completed request not yet collected and returns its ticket and client
+ * (client nullable), in completion order, each once.  It does not collect the
+ * request: pass the ticket to jx_server_wait.  A request's results occupy the
+ * server's pinned staging memory (min(budget, 2 GiB)) from its launch until it
+ * is collected, and a request is launched only when its results fit, so
+ * callers should collect what completes. */
+jx_status jx_server_wait_any(jx_server* srv, double timeout_s, uint64_t* ticket, int32_t* client);
+
+/* Releases the client once its queued requests have completed; a client still
+ * waiting for admission is admitted first if it has queued requests, else it
+ * leaves the admission queue at once.  Results of its requests stay
+ * collectable with jx_server_wait after the close.  No request may be
+ * submitted to a closed client. */
 jx_status jx_server_close(jx_server* srv, int32_t client);
 
 /* Counters: launches, requests, envs stepped, admission waits, bytes in use. */

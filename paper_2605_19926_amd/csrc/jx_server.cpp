@@ -3,15 +3,21 @@
 // persistent launches (continuous batching).
 //
 // Threads:
-//   caller threads  jx_server_open / submit / wait / close (any number)
-//   scheduler       admits clients (HBM budget, FIFO), packs every ready request
-//                   (its client has no step in flight) into one launch on the
-//                   next free stream: H2D actions, descriptors, work items; the
-//                   serving kernel; D2H frames/rewards/dones; an event
-//   completion      waits for launch events in order, copies each request's
-//                   results out of its client's pinned buffers and completes it
-// A request that arrives while launches are in flight joins the next launch,
-// which can start on another stream before the earlier ones finish.
+//   caller threads  jx_server_open / submit / wait / close (any number); open
+//                   generates the client's layouts on the caller's thread
+//   admitter        admits queued clients in FIFO order as the HBM budget
+//                   allows: upload of the state image and the episode-0 reset
+//   scheduler       packs every ready request (its client has no step in
+//                   flight, its results fit the staging arena) into one launch
+//                   on the next free stream: H2D actions, descriptors, work
+//                   items; the serving kernel; D2H frames/rewards/dones into
+//                   the request's range of the pinned staging arena; an event
+//   completion      polls the in-flight launches and retires each as it
+//                   completes (any stream order), stamping its requests
+// A caller's wait copies a request's results out of the staging arena and
+// releases its range.  A request that arrives while launches are in flight
+// joins the next launch, which can start on another stream before the earlier
+// ones finish.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -87,20 +93,32 @@ struct Request {
   uint64_t ticket = 0;
   int client = -1;
   std::vector<uint8_t> actions;
-  std::vector<uint8_t> obs;
-  std::vector<float> rew;
-  std::vector<uint8_t> done;
+  // range of the pinned staging arena, reserved when the request is launched:
+  // actions | frames | rewards | dones (each 256-byte aligned); released when
+  // the caller collects the request
+  int64_t h_off = -1, h_len = 0;
+  uint8_t* h_act = nullptr;
+  uint8_t* h_obs = nullptr;
+  float* h_rew = nullptr;
+  uint8_t* h_done = nullptr;
+  int64_t obs_bytes = 0;
+  int n = 0;
   double t_submit = 0, t_done = 0;
   int status = 0;  // 0 queued, 1 launched, 2 done, 3 failed
 };
 
-enum ClientState { PENDING, ACTIVE, CLOSED };
+// PENDING: in the admission queue; ADMITTING: memory reserved, being
+// uploaded and reset (without the server lock); ACTIVE: served.
+enum ClientState { PENDING, ADMITTING, ACTIVE, CLOSED };
 
 struct Client {
   int id = -1;
   int n = 0;
   jx_env_cfg cfg{};
   std::vector<uint64_t> seeds;
+  // state image (layouts generated on the host at open), uploaded on admission
+  std::vector<uint8_t> img;
+  std::vector<int32_t> idx;
   ClientState st = PENDING;
   bool closing = false;
   bool in_flight = false;
@@ -110,11 +128,6 @@ struct Client {
   DevState S{};
   DevIo io{};
   int64_t obs_bytes = 0;
-  // pinned host staging
-  uint8_t* h_act = nullptr;
-  uint8_t* h_obs = nullptr;
-  float* h_rew = nullptr;
-  uint8_t* h_done = nullptr;
   std::deque<std::shared_ptr<Request>> queue;
 };
 
@@ -143,42 +156,16 @@ constexpr int kMaxItemsPerLaunch = 1 << 18;
 
 }  // namespace
 
-// Pinned host buffers are recycled, not freed: freeing pinned memory can
-// synchronise the device, which would stall every client's requests.
-class PinnedPool {
- public:
-  void* get(size_t bytes) {
-    std::lock_guard<std::mutex> g(mu_);
-    auto it = free_.lower_bound(bytes);
-    if (it != free_.end() && it->first <= 2 * bytes + 4096) {
-      void* p = it->second;
-      size_[p] = it->first;
-      free_.erase(it);
-      return p;
-    }
-    void* p = nullptr;
-    if (hipHostMalloc(&p, bytes) != hipSuccess) return nullptr;
-    size_[p] = bytes;
-    return p;
-  }
-  void put(void* p) {
-    if (!p) return;
-    std::lock_guard<std::mutex> g(mu_);
-    free_.emplace(size_[p], p);
-  }
-  ~PinnedPool() {
-    for (auto& kv : free_) (void)hipHostFree(kv.second);
-  }
-
- private:
-  std::mutex mu_;
-  std::multimap<size_t, void*> free_;
-  std::map<void*, size_t> size_;
-};
+// Pinned staging arena for requests' actions and results: allocated once, so
+// that no pinned allocation or free (which can synchronise the device) happens
+// while serving.
+constexpr int64_t kStagingMaxBytes = int64_t(2) << 30;
 
 struct jx_server {
   int device = 0;
-  PinnedPool pinned;
+  uint8_t* host_base = nullptr;  // pinned staging arena
+  int64_t host_bytes = 0;
+  Arena host;
   int mode = JX_SERVE_COALESCE;
   int max_batch_envs = 0;
   int n_cu = 1;
@@ -191,18 +178,20 @@ struct jx_server {
 
   std::mutex mu;
   std::condition_variable cv_sched;   // scheduler: new work / stream freed / stop
+  std::condition_variable cv_admit;   // admitter: a client queued / memory freed / stop
   std::condition_variable cv_done;    // waiters: a request completed
   std::condition_variable cv_comp;    // completion thread: a launch was issued
   std::map<int, std::unique_ptr<Client>> clients;
   std::deque<int> pending;            // admission FIFO
   std::map<uint64_t, std::shared_ptr<Request>> requests;
   std::deque<Launch> inflight;
+  std::deque<std::pair<uint64_t, int>> completed;  // (ticket, client) in completion order
   uint64_t next_ticket = 1;
   int next_client = 0;
   bool stop = false;
   std::string fatal;
   jx_server_stats stats{};
-  std::thread sched, comp;
+  std::thread sched, comp, admitter;
 };
 
 namespace {
@@ -215,15 +204,10 @@ int64_t client_bytes(int n, const jx_env_cfg& cfg, Layout* L, int64_t* obs_bytes
          align256(n);
 }
 
-// Uploads a freshly generated image and runs the episode-0 reset.  Called
-// without the server lock; the client's arena range is already reserved.
+// Uploads the client's image (built at open) and runs the episode-0 reset.
+// Called without the server lock; the client's arena range is already reserved.
 jx_status activate(jx_server* s, Client* c) {
-  std::vector<uint8_t> img;
-  Layout L;
-  std::vector<int64_t> oo;
-  std::vector<int32_t> idx;
-  jx_status st = build_image(c->n, c->seeds.data(), &c->cfg, 1, nullptr, &img, &L, &oo, &idx);
-  if (st) return st;
+  const Layout L = c->L;
   uint8_t* base = s->arena_base + c->arena_off;
   uint8_t* ws = base;
   uint8_t* obs = ws + align256(L.total);
@@ -232,63 +216,81 @@ jx_status activate(jx_server* s, Client* c) {
   uint8_t* dn = rew + align256(4 * (int64_t)c->n);
   c->L = L;
   c->S = bind_state(ws, L, c->n);
-  set_uniform(&c->S, &c->cfg, 1, idx);
+  set_uniform(&c->S, &c->cfg, 1, c->idx);
   c->io = DevIo{};
   c->io.act = act;
   c->io.obs = obs;
   c->io.rew = (float*)rew;
   c->io.done = dn;
   c->io.mode = MODE_STEP;
-  c->h_act = (uint8_t*)s->pinned.get(std::max(c->n, 1));
-  c->h_obs = (uint8_t*)s->pinned.get(std::max<int64_t>(c->obs_bytes, 1));
-  c->h_rew = (float*)s->pinned.get(4 * (size_t)std::max(c->n, 1));
-  c->h_done = (uint8_t*)s->pinned.get(std::max(c->n, 1));
-  if (!c->h_act || !c->h_obs || !c->h_rew || !c->h_done) return set_error(JX_ENOMEM, "pinned host buffers");
-  if (hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, s->admin) != hipSuccess)
+  if (hipMemcpyAsync(ws, c->img.data(), c->img.size(), hipMemcpyHostToDevice, s->admin) != hipSuccess)
     return set_error(JX_EDEVICE, "client upload failed");
   DevIo io{};
   io.mode = MODE_RESET;
   int rc = launch_batch(c->S, io, nullptr, 0, LaunchCfg{0, 1, 1, 0}, c->cfg.side, s->n_cu, 0, s->admin);
   if (rc) return set_error(JX_EDEVICE, std::string("client reset: ") + kernel_error_string(rc));
   if (hipStreamSynchronize(s->admin) != hipSuccess) return set_error(JX_EDEVICE, "client reset sync failed");
+  std::vector<uint8_t>().swap(c->img);
   return JX_OK;
 }
 
 void free_client_memory(jx_server* s, Client* c) {
   if (c->arena_off >= 0) s->arena.release(c->arena_off, c->bytes);
   c->arena_off = -1;
-  s->pinned.put(c->h_act);
-  s->pinned.put(c->h_obs);
-  s->pinned.put(c->h_rew);
-  s->pinned.put(c->h_done);
-  c->h_act = c->h_obs = c->h_done = nullptr;
-  c->h_rew = nullptr;
 }
 
-// Admits pending clients in FIFO order while the budget allows (lock held on
-// entry and exit; released around the device work).
-void admit_pending(jx_server* s, std::unique_lock<std::mutex>& lk) {
-  while (!s->pending.empty()) {
+// Staging bytes of one request of a client: actions, frames, rewards, dones.
+int64_t staging_bytes(int n, int64_t obs_bytes) {
+  return align256(n) + align256(obs_bytes) + align256(4 * (int64_t)n) + align256(n);
+}
+
+// Returns a request's staging range to the arena (lock held).
+void release_staging(jx_server* s, Request* r) {
+  if (r->h_off >= 0) s->host.release(r->h_off, r->h_len);
+  r->h_off = -1;
+  r->h_act = r->h_obs = r->h_done = nullptr;
+  r->h_rew = nullptr;
+}
+
+// Admitter thread: admits queued clients in FIFO order while the budget
+// allows, uploading and resetting each without the server lock, so the
+// scheduler keeps issuing launches meanwhile.
+void admitter_main(jx_server* s) {
+  hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    if (s->pending.empty()) {
+      s->cv_admit.wait(lk);
+      continue;
+    }
     Client* c = s->clients[s->pending.front()].get();
     const int64_t off = s->arena.alloc(c->bytes);
-    if (off < 0) return;
+    if (off < 0) {
+      s->cv_admit.wait(lk);  // woken when a client's memory is released
+      continue;
+    }
     c->arena_off = off;
+    c->st = ADMITTING;
     s->pending.pop_front();
     lk.unlock();
     jx_status st = activate(s, c);
     lk.lock();
+    s->stats.clients_pending -= 1;
     if (st != JX_OK) {
       s->fatal = "admission failed: " + std::string(jx_last_error());
       c->st = CLOSED;
-      for (auto& r : c->queue) r->status = 3;
+      for (auto& r : c->queue) {
+        r->status = 3;
+        s->completed.emplace_back(r->ticket, r->client);
+      }
       c->queue.clear();
       free_client_memory(s, c);
       s->cv_done.notify_all();
       continue;
     }
     c->st = ACTIVE;
-    s->stats.clients_pending -= 1;
     s->stats.clients_active += 1;
+    s->cv_sched.notify_one();
   }
 }
 
@@ -304,6 +306,7 @@ void reap_closed(jx_server* s) {
     }
   }
   if (freed) {
+    s->cv_admit.notify_one();
     for (auto it = s->clients.begin(); it != s->clients.end();) {
       if (it->second->st == CLOSED && it->second->queue.empty()) it = s->clients.erase(it);
       else ++it;
@@ -312,7 +315,7 @@ void reap_closed(jx_server* s) {
 }
 
 // Builds and issues one launch on stream slot k from the ready clients.
-void issue(jx_server* s, int k, std::vector<Client*>& batch) {
+void issue(jx_server* s, int k, std::vector<Client*>& batch, const std::vector<int64_t>& stage) {
   StreamSlot& ss = s->streams[k];
   Launch L;
   L.stream = k;
@@ -324,16 +327,26 @@ void issue(jx_server* s, int k, std::vector<Client*>& batch) {
     c->queue.pop_front();
     c->in_flight = true;
     r->status = 1;
+    r->n = c->n;
+    r->obs_bytes = c->obs_bytes;
+    r->h_off = stage[d];
+    r->h_len = staging_bytes(c->n, c->obs_bytes);
+    uint8_t* h = s->host_base + r->h_off;
+    r->h_act = h;
+    r->h_obs = h + align256(c->n);
+    r->h_rew = (float*)(r->h_obs + align256(c->obs_bytes));
+    r->h_done = (uint8_t*)r->h_rew + align256(4 * (int64_t)c->n);
     L.reqs.push_back(r);
-    std::memcpy(c->h_act, r->actions.data(), c->n);
+    std::memcpy(r->h_act, r->actions.data(), c->n);
     ss.h_states[d] = c->S;
     ss.h_ios[d] = c->io;
     for (int e = 0; e < c->n; ++e) ss.h_items[n_items++] = ServeItem{(int32_t)d, e};
   }
   hipStream_t st = ss.s;
   bool ok = true;
-  for (Client* c : batch)
-    ok = ok && hipMemcpyAsync((void*)c->io.act, c->h_act, c->n, hipMemcpyHostToDevice, st) == hipSuccess;
+  for (size_t d = 0; d < batch.size(); ++d)
+    ok = ok && hipMemcpyAsync((void*)batch[d]->io.act, L.reqs[d]->h_act, batch[d]->n,
+                              hipMemcpyHostToDevice, st) == hipSuccess;
   if (s->mode == JX_SERVE_PLAIN) {
     Client* c = batch[0];
     ok = ok && launch_batch(c->S, c->io, nullptr, 0, LaunchCfg{0, 1, 1, 0}, c->cfg.side, s->n_cu, 0, st) == 0;
@@ -351,15 +364,20 @@ void issue(jx_server* s, int k, std::vector<Client*>& batch) {
                             groups, st) == 0;
     if (ok) ss.seq += 1;
   }
-  for (Client* c : batch) {
-    ok = ok && hipMemcpyAsync(c->h_obs, c->io.obs, c->obs_bytes, hipMemcpyDeviceToHost, st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(c->h_rew, c->io.rew, 4 * (size_t)c->n, hipMemcpyDeviceToHost, st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(c->h_done, c->io.done, c->n, hipMemcpyDeviceToHost, st) == hipSuccess;
+  for (size_t d = 0; d < batch.size(); ++d) {
+    Client* c = batch[d];
+    Request* r = L.reqs[d].get();
+    ok = ok && hipMemcpyAsync(r->h_obs, c->io.obs, c->obs_bytes, hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(r->h_rew, c->io.rew, 4 * (size_t)c->n, hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(r->h_done, c->io.done, c->n, hipMemcpyDeviceToHost, st) == hipSuccess;
   }
   ok = ok && hipEventRecord(ss.ev, st) == hipSuccess;
   if (!ok) {
     s->fatal = "launch failed";
-    for (auto& r : L.reqs) r->status = 3;
+    for (auto& r : L.reqs) {
+      r->status = 3;
+      s->completed.emplace_back(r->ticket, r->client);
+    }
     for (Client* c : batch) c->in_flight = false;
     s->cv_done.notify_all();
     return;
@@ -376,7 +394,6 @@ void scheduler_main(jx_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
     reap_closed(s);
-    admit_pending(s, lk);
     // ready clients, oldest request first
     std::vector<Client*> ready;
     for (auto& kv : s->clients) {
@@ -399,62 +416,78 @@ void scheduler_main(jx_server* s) {
       return a->queue.front()->ticket < b->queue.front()->ticket;
     });
     std::vector<Client*> batch;
+    std::vector<int64_t> stage;
     int envs = 0;
     for (Client* c : ready) {
       if (s->mode == JX_SERVE_PLAIN && !batch.empty()) break;
       if (!batch.empty() && s->max_batch_envs > 0 && envs + c->n > s->max_batch_envs) continue;
       if ((int)batch.size() >= kMaxClientsPerLaunch || envs + c->n > kMaxItemsPerLaunch) break;
+      // results must fit the staging arena; else the request waits for a
+      // caller to collect earlier results
+      const int64_t off = s->host.alloc(staging_bytes(c->n, c->obs_bytes));
+      if (off < 0) continue;
       batch.push_back(c);
+      stage.push_back(off);
       envs += c->n;
     }
+    if (batch.empty()) {
+      s->cv_sched.wait(lk);
+      continue;
+    }
     s->next_stream = (k + 1) % (int)s->streams.size();
-    issue(s, k, batch);
+    issue(s, k, batch, stage);
   }
 }
 
+// Retires launches in the order they complete (any stream), stamping their
+// requests' completion time.  Results are already in the requests' pinned
+// buffers; the caller's wait copies them out, so nothing here delays the next
+// launch's timestamp.
 void completion_main(jx_server* s) {
   hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (true) {
     while (s->inflight.empty() && !s->stop) s->cv_comp.wait(lk);
     if (s->inflight.empty() && s->stop) return;
-    hipEvent_t ev = s->inflight.front().ev;
-    lk.unlock();
-    hipError_t e = hipEventSynchronize(ev);
-    const double t = now_s();
-    lk.lock();
-    Launch L = std::move(s->inflight.front());
-    s->inflight.pop_front();
-    // Copy the results out of the clients' pinned buffers without the lock:
-    // those clients stay in flight (no new launch touches their buffers) until
-    // the copies are done.
-    std::vector<Client*> owners(L.reqs.size(), nullptr);
-    for (size_t k = 0; k < L.reqs.size(); ++k) {
-      auto it = s->clients.find(L.reqs[k]->client);
-      owners[k] = it == s->clients.end() ? nullptr : it->second.get();
-    }
-    lk.unlock();
-    for (size_t k = 0; k < L.reqs.size(); ++k) {
-      Request* r = L.reqs[k].get();
-      Client* c = owners[k];
-      if (e == hipSuccess && c) {
-        r->obs.assign(c->h_obs, c->h_obs + c->obs_bytes);
-        r->rew.assign(c->h_rew, c->h_rew + c->n);
-        r->done.assign(c->h_done, c->h_done + c->n);
+    bool retired = false;
+    for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+      const hipError_t e = hipEventQuery(it->ev);
+      if (e == hipErrorNotReady) {
+        ++it;
+        continue;
+      }
+      const double t = now_s();
+      for (auto& r : it->reqs) {
+        r->status = (e == hipSuccess) ? 2 : 3;
+        r->t_done = t;
+        s->completed.emplace_back(r->ticket, r->client);
+        auto c = s->clients.find(r->client);
+        if (c != s->clients.end()) c->second->in_flight = false;
+        s->stats.requests += 1;
+      }
+      if (e != hipSuccess) s->fatal = std::string("device error: ") + hipGetErrorString(e);
+      s->streams[it->stream].busy = false;
+      it = s->inflight.erase(it);
+      retired = true;
+      // requests collected through jx_server_wait leave stale entries in the
+      // completion queue: prune them once they dominate (amortised O(1))
+      if (s->completed.size() > 2 * s->requests.size() + 1024) {
+        std::deque<std::pair<uint64_t, int>> keep;
+        for (auto& tc : s->completed)
+          if (s->requests.count(tc.first)) keep.push_back(tc);
+        s->completed.swap(keep);
       }
     }
-    lk.lock();
-    for (size_t k = 0; k < L.reqs.size(); ++k) {
-      Request* r = L.reqs[k].get();
-      r->status = (e == hipSuccess && owners[k]) ? 2 : 3;
-      r->t_done = t;
-      if (owners[k]) owners[k]->in_flight = false;
-      s->stats.requests += 1;
+    if (retired) {
+      s->cv_done.notify_all();
+      s->cv_sched.notify_one();
+    } else {
+      // nothing finished yet: poll again shortly (launches take tens of
+      // microseconds and up)
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(10));
+      lk.lock();
     }
-    if (e != hipSuccess) s->fatal = std::string("device error: ") + hipGetErrorString(e);
-    s->streams[L.stream].busy = false;
-    s->cv_done.notify_all();
-    s->cv_sched.notify_one();
   }
 }
 
@@ -492,6 +525,9 @@ jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_by
   s->n_cu = std::max(1, p.multiProcessorCount);
   SRV_CHK(hipMalloc((void**)&s->arena_base, hbm_budget_bytes), "HBM budget allocation failed");
   s->arena.init((int64_t)hbm_budget_bytes);
+  s->host_bytes = std::min<int64_t>((int64_t)hbm_budget_bytes, kStagingMaxBytes);
+  SRV_CHK(hipHostMalloc((void**)&s->host_base, (size_t)s->host_bytes), "pinned staging allocation failed");
+  s->host.init(s->host_bytes);
   SRV_CHK(hipStreamCreateWithFlags(&s->admin, hipStreamNonBlocking), "stream");
   const int ns = (mode == JX_SERVE_PLAIN) ? 1 : n_streams;
   s->streams.resize(ns);
@@ -510,6 +546,7 @@ jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_by
   SRV_CHK(hipDeviceSynchronize(), "sync");
   s->sched = std::thread(scheduler_main, s);
   s->comp = std::thread(completion_main, s);
+  s->admitter = std::thread(admitter_main, s);
   *out = s;
   return JX_OK;
 }
@@ -522,11 +559,14 @@ void jx_server_destroy(jx_server* s) {
   }
   s->cv_sched.notify_all();
   s->cv_comp.notify_all();
+  s->cv_admit.notify_all();
   if (s->sched.joinable()) s->sched.join();
   if (s->comp.joinable()) s->comp.join();
+  if (s->admitter.joinable()) s->admitter.join();
   hipSetDevice(s->device);
   hipDeviceSynchronize();
   for (auto& kv : s->clients) free_client_memory(s, kv.second.get());
+  if (s->host_base) hipHostFree(s->host_base);
   for (auto& ss : s->streams) {
     if (ss.s) hipStreamDestroy(ss.s);
     if (ss.ev) hipEventDestroy(ss.ev);
@@ -555,6 +595,19 @@ jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, co
   c->seeds.assign(seeds, seeds + n_envs);
   c->bytes = client_bytes(n_envs, *cfg, &c->L, &c->obs_bytes);
   if (c->bytes > s->budget) return set_error(JX_ENOMEM, "client exceeds the HBM budget on its own");
+  if (staging_bytes(n_envs, c->obs_bytes) > s->host_bytes)
+    return set_error(JX_ENOMEM, "client's step results exceed the pinned staging arena");
+  {
+    // layouts are generated here, on the caller's thread, so that admission
+    // only uploads and resets
+    Layout L;
+    std::vector<int64_t> oo;
+    jx_status st = build_image(n_envs, c->seeds.data(), &c->cfg, 1, nullptr, &c->img, &L, &oo, &c->idx);
+    if (st) return st;
+    if (L.total != c->L.total || (int64_t)c->img.size() > L.total)
+      return set_error(JX_ESTATE, "client image does not match its reserved layout");
+    c->L = L;
+  }
   std::unique_lock<std::mutex> lk(s->mu);
   const int id = s->next_client++;
   c->id = id;
@@ -567,15 +620,22 @@ jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, co
     s->pending.push_back(id);
     s->stats.clients_pending += 1;
     s->stats.admission_waits += 1;
+    s->cv_admit.notify_one();
     return JX_EBUSY;
   }
   cp->arena_off = off;
+  cp->st = ADMITTING;
   lk.unlock();
   jx_status st = activate(s, cp);
   lk.lock();
   if (st != JX_OK) {
     free_client_memory(s, cp);
+    for (auto& r : cp->queue) {
+      r->status = 3;
+      s->completed.emplace_back(r->ticket, r->client);
+    }
     s->clients.erase(id);
+    s->cv_done.notify_all();
     return st;
   }
   cp->st = ACTIVE;
@@ -623,12 +683,41 @@ jx_status jx_server_wait(jx_server* s, uint64_t ticket, double timeout_s, uint8_
     s->requests.erase(ticket);
     fatal = s->fatal;
   }
-  // the request is ours alone now: copy without the lock
-  if (r->status == 3) return set_error(JX_EDEVICE, fatal.empty() ? "request failed" : fatal);
-  if (obs) std::memcpy(obs, r->obs.data(), r->obs.size());
-  if (rew) std::memcpy(rew, r->rew.data(), 4 * r->rew.size());
-  if (done) std::memcpy(done, r->done.data(), r->done.size());
-  if (latency) *latency = r->t_done - r->t_submit;
+  // the request is ours alone now: copy without the lock, then give its
+  // staging range back
+  const bool failed = r->status == 3;
+  if (!failed) {
+    if (obs) std::memcpy(obs, r->h_obs, (size_t)r->obs_bytes);
+    if (rew) std::memcpy(rew, r->h_rew, 4 * (size_t)r->n);
+    if (done) std::memcpy(done, r->h_done, (size_t)r->n);
+    if (latency) *latency = r->t_done - r->t_submit;
+  }
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    release_staging(s, r.get());
+  }
+  s->cv_sched.notify_one();
+  if (failed) return set_error(JX_EDEVICE, fatal.empty() ? "request failed" : fatal);
+  return JX_OK;
+}
+
+jx_status jx_server_wait_any(jx_server* s, double timeout_s, uint64_t* ticket, int32_t* client) {
+  if (!s || !ticket) return set_error(JX_EINVAL, "null argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto next = [&] {
+    // drop entries already collected through jx_server_wait
+    while (!s->completed.empty() && !s->requests.count(s->completed.front().first))
+      s->completed.pop_front();
+    return !s->completed.empty();
+  };
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, next);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), next)) {
+    return JX_EBUSY;
+  }
+  *ticket = s->completed.front().first;
+  if (client) *client = s->completed.front().second;
+  s->completed.pop_front();
   return JX_OK;
 }
 
@@ -638,16 +727,15 @@ jx_status jx_server_close(jx_server* s, int32_t client) {
   auto it = s->clients.find(client);
   if (it == s->clients.end()) return set_error(JX_EINVAL, "unknown client");
   Client* c = it->second.get();
-  if (c->st == PENDING) {
-    // never admitted: drop it from the FIFO and fail its queued requests
+  if (c->st == PENDING && c->queue.empty()) {
+    // never admitted and nothing to run: leave the admission FIFO at once
     s->pending.erase(std::remove(s->pending.begin(), s->pending.end(), client), s->pending.end());
-    for (auto& r : c->queue) r->status = 3;
-    c->queue.clear();
     c->st = CLOSED;
     s->stats.clients_pending -= 1;
     s->clients.erase(it);
-    s->cv_done.notify_all();
   } else {
+    // admitted (or still to be admitted, with queued requests): released once
+    // its queued requests have run
     c->closing = true;
   }
   s->cv_sched.notify_one();

@@ -103,6 +103,7 @@ _SIGS = {
     "jx_server_wait": (_i32, [_vp, _u64, ctypes.c_double, _vp, _vp, _vp,
                               ctypes.POINTER(ctypes.c_double)]),
     "jx_server_close": (_i32, [_vp, _i32]),
+    "jx_server_wait_any": (_i32, [_vp, ctypes.c_double, ctypes.POINTER(_u64), ctypes.POINTER(_i32)]),
     "jx_server_get_stats": (_i32, [_vp, ctypes.POINTER(jx_server_stats)]),
 }
 
@@ -390,12 +391,22 @@ class Server:
         check(lib().jx_server_submit(self.h, client, a.ctypes.data, ctypes.byref(t)))
         return t.value
 
-    def wait(self, client: int, ticket: int, timeout: float = -1.0, want_obs: bool = True):
-        """Returns (obs [n, H*W*3] or None, reward, done, latency_s), or None on timeout."""
+    def wait(self, client: int, ticket: int, timeout: float = -1.0, want_obs: bool = True,
+             out=None):
+        """Returns (obs [n, H*W*3] or None, reward, done, latency_s), or None on
+        timeout.  `out` = (obs, reward, done) arrays to fill instead of new ones."""
         n, fb = self.sizes[client]
-        obs = np.empty((n, fb), np.uint8) if want_obs else None
-        rew = np.empty(n, np.float32)
-        done = np.empty(n, np.uint8)
+        if out is not None:
+            obs, rew, done = out
+            if (obs is not None and (obs.dtype != np.uint8 or obs.size != n * fb or
+                                     not obs.flags.c_contiguous)) or \
+                    rew.dtype != np.float32 or rew.size != n or not rew.flags.c_contiguous or \
+                    done.dtype != np.uint8 or done.size != n or not done.flags.c_contiguous:
+                raise JxError(JX_EINVAL, "out buffers do not match the client's sizes")
+        else:
+            obs = np.empty((n, fb), np.uint8) if want_obs else None
+            rew = np.empty(n, np.float32)
+            done = np.empty(n, np.uint8)
         lat = ctypes.c_double()
         rc = lib().jx_server_wait(self.h, ticket, timeout, _ptr(obs), rew.ctypes.data,
                                   done.ctypes.data, ctypes.byref(lat))
@@ -403,6 +414,17 @@ class Server:
             return None
         check(rc)
         return obs, rew, done, lat.value
+
+    def wait_any(self, timeout: float = -1.0):
+        """Next completed, not yet collected request as (client, ticket), in
+        completion order, or None on timeout.  Collect it with wait()."""
+        tk = _u64()
+        cid = _i32()
+        rc = lib().jx_server_wait_any(self.h, timeout, ctypes.byref(tk), ctypes.byref(cid))
+        if rc == JX_EBUSY:
+            return None
+        check(rc)
+        return cid.value, tk.value
 
     def close_client(self, client: int):
         check(lib().jx_server_close(self.h, client))

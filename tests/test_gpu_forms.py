@@ -311,6 +311,39 @@ def test_serving_alone_equals_mix_equals_plain():
     assert all(len(v) == T for v in results.values())
 
 
+def test_serving_completion_queue():
+    """wait_any hands out every completed request once, in completion order,
+    and the results collected through it equal those of a plain wait."""
+    from paper_2605_19926_amd import jx
+    cfg = W.env_cfg(side=16, obs_h=64, obs_w=64)
+    got_any, got_plain = {}, {}
+    for use_any in (True, False):
+        srv = jx.Server(hbm_budget=1 << 30, n_streams=2)
+        cids = [srv.open(W.seeds(90 + k, 5 + 7 * k), cfg)[0] for k in range(3)]
+        tickets = {}
+        for t in range(4):
+            for k, cid in enumerate(cids):
+                acts = W.actions(95 + k, 4, 5 + 7 * k, 6)[t]
+                tickets[srv.submit(cid, acts)] = (k, t)
+        out = got_any if use_any else got_plain
+        if use_any:
+            seen = set()
+            for _ in range(len(tickets)):
+                cid, tk = srv.wait_any(timeout=30.0)
+                assert tk in tickets and tk not in seen
+                seen.add(tk)
+                out[tickets[tk]] = srv.wait(cid, tk)
+            assert srv.wait_any(timeout=0.0) is None
+        else:
+            for tk, (k, t) in tickets.items():
+                out[(k, t)] = srv.wait(cids[k], tk)
+        srv.close()
+    assert got_any.keys() == got_plain.keys()
+    for key in got_any:
+        for a, b in zip(got_any[key][:3], got_plain[key][:3]):
+            assert np.array_equal(a, b)
+
+
 def test_serving_admission_by_budget():
     from paper_2605_19926_amd import jx
     cfg = W.env_cfg(side=32, obs_h=84, obs_w=84)
@@ -327,10 +360,19 @@ def test_serving_admission_by_budget():
     assert not ok
     tk = srv.submit(cid, np.zeros(2000, np.uint8))
     assert srv.wait(cid, tk, timeout=0.2) is None        # still queued for admission
+    # closing a queued client keeps its queued request: it is admitted, runs it,
+    # and the result stays collectable after the close
+    srv.close_client(cid)
+    # a queued client with nothing to run leaves the admission queue at once
+    idle, ok = srv.open(W.seeds(81, 2000), cfg)
+    assert not ok
+    srv.close_client(idle)
     for c in ids:
         srv.close_client(c)
     res = srv.wait(cid, tk, timeout=60.0)
     assert res is not None and res[1].shape == (2000,)
+    assert res[0].shape == (2000, 84 * 84 * 3)
     st = srv.stats()
-    assert st["admission_waits"] >= 1
+    assert st["admission_waits"] >= 2
+    assert st["clients_pending"] == 0
     srv.close()
