@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define JX_ABI_VERSION 1
+#define JX_ABI_VERSION 2
 
 typedef int32_t jx_status;
 #define JX_OK 0
@@ -49,7 +49,8 @@ typedef int32_t jx_status;
 
 /* Per-environment configuration.  Limits: side 5..64 (tile-grid side N),
  * n_colors 1..8, loop_frac 0..1, max_decor 0..2, obs_h even and 2..128,
- * obs_w a multiple of 4 in 4..128, n_actions 4 or 6, episode_cap >= 1.
+ * obs_w a multiple of 4 in 4..128, n_actions 4 or 6, episode_cap >= 1,
+ * shade_levels 0..16 (shade_dist > 0 when shading is on).
  * Values used by the workloads: fov 60, move 0.1, turn pi/16, pickup 0.3. */
 typedef struct {
   int32_t side;          /* N: the map is N x N tiles, border tiles are walls */
@@ -66,6 +67,14 @@ typedef struct {
   float turn;            /* radians per turn action */
   float pickup_radius;   /* key pickup radius, tiles */
   float r_goal, r_key;   /* rewards */
+  /* Distance shading of walls (the paper's ray-casting section allows a shading
+   * colour by the hit distance; the rule is this library's reading).  With
+   * S = shade_levels > 0 a column hit at perpendicular distance t* is drawn at
+   * level l = min(floor(t* * S / shade_dist), S - 1): each channel of its wall
+   * colour (after the side darkening) becomes floor(c * (S - l) / S).
+   * Sprites, ceiling and floor are not shaded.  0 = off. */
+  int32_t shade_levels;
+  float shade_dist;
 } jx_env_cfg;
 
 typedef struct jx_ctx jx_ctx;

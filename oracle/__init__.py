@@ -27,7 +27,7 @@ _LIB = os.path.join(_HERE, "libjxoracle.so")
 EV_BLOCKED_X, EV_BLOCKED_Y, EV_KEY, EV_GOAL = 0x01, 0x02, 0x04, 0x08
 EV_TRUNC, EV_INVALID, EV_RESET = 0x10, 0x20, 0x40
 SF_MOVE, SF_KEY, SF_GOAL = 0x01, 0x02, 0x04
-CF_DDA, CF_SPAN, CF_SPRITE, CF_MULTI = 0x01, 0x02, 0x04, 0x08
+CF_DDA, CF_SPAN, CF_SPRITE, CF_MULTI, CF_SHADE = 0x01, 0x02, 0x04, 0x08, 0x10
 MAX_DECOR = 2
 
 
@@ -49,7 +49,8 @@ class OrcCfg(ctypes.Structure):
                 ("fov_deg", ctypes.c_double), ("n_actions", ctypes.c_int32),
                 ("episode_cap", ctypes.c_int32), ("move", ctypes.c_double),
                 ("turn", ctypes.c_double), ("pickup_radius", ctypes.c_double),
-                ("r_goal", ctypes.c_double), ("r_key", ctypes.c_double)]
+                ("r_goal", ctypes.c_double), ("r_key", ctypes.c_double),
+                ("shade_levels", ctypes.c_int32), ("shade_dist", ctypes.c_double)]
 
 
 class OrcState(ctypes.Structure):
@@ -66,7 +67,8 @@ class OrcState(ctypes.Structure):
                 "n_decor": self.n_decor, "decor": list(self.decor)}
 
 
-_FLOAT_FIELDS = ("loop_frac", "fov_deg", "move", "turn", "pickup_radius", "r_goal", "r_key")
+_FLOAT_FIELDS = ("loop_frac", "fov_deg", "move", "turn", "pickup_radius", "r_goal", "r_key",
+                 "shade_dist")
 
 
 def make_cfg(d: dict) -> OrcCfg:

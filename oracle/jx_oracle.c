@@ -529,6 +529,20 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
     uint8_t wc[3];
     const uint8_t* base = (o.hit == door && !dopen) ? kDoor : kPal[(o.hit < 0 ? 0 : o.hit) % K];
     for (int32_t ch = 0; ch < 3; ++ch) wc[ch] = o.side ? (uint8_t)(base[ch] >> 1) : base[ch];
+    if (cfg->shade_levels > 0) {
+      /* Distance shading (the ray-casting section lets the wall colour depend
+       * on the hit distance; this is the library's reading): S levels over
+       * [0, D), level l = floor(t* S / D) capped at S - 1, and each channel of
+       * the wall colour keeps the fraction (S - l) / S, rounded down. */
+      const int32_t S = cfg->shade_levels;
+      const double q = o.t * (double)S / cfg->shade_dist;
+      int32_t lv = (int32_t)floor(q);
+      if (lv > S - 1) lv = S - 1;
+      for (int32_t ch = 0; ch < 3; ++ch) wc[ch] = (uint8_t)((wc[ch] * (S - lv)) / S);
+      /* F4: the level boundaries are the integers 1..S-1 of q */
+      for (int32_t k = 1; k < S; ++k)
+        if (fabs(q - k) <= 1e-5 * q) fl[col] |= ORC_CF_SHADE;
+    }
     double hh = H / (2.0 * o.t);
     for (int32_t k = 0; k < H / 2; ++k)
       if (fabs(hh - (k + 0.5)) <= 1e-5 * hh) fl[col] |= ORC_CF_SPAN;

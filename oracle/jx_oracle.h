@@ -45,6 +45,8 @@ typedef struct {
   int32_t n_actions;     /* 4 or 6 */
   int32_t episode_cap;   /* truncation length */
   double move, turn, pickup_radius, r_goal, r_key;
+  int32_t shade_levels;  /* S: distance-shading levels, 0 = off */
+  double shade_dist;     /* D: distance at which the last level starts */
 } orc_cfg;
 
 /* Per-environment state.  Positions in tile units, heading in radians from +x
@@ -77,6 +79,7 @@ typedef struct {
 #define ORC_CF_SPAN   0x02  /* F2: wall span boundary within the window of a pixel centre */
 #define ORC_CF_SPRITE 0x04  /* F3: a sprite comparison within its window */
 #define ORC_CF_MULTI  0x08  /* more than one F1 tie on the walk */
+#define ORC_CF_SHADE  0x10  /* F4: t* S / D within the window of a shading level boundary */
 
 /* ---- random numbers ---------------------------------------------------- */
 uint64_t orc_rng_next(uint64_t* s);                 /* SplitMix64 step */

@@ -74,6 +74,9 @@ bool validate_cfg(const jx_env_cfg& c, std::string* why) {
       !std::isfinite(c.r_key) || !(c.pickup_radius >= 0.f) || !std::isfinite(c.pickup_radius))
     return bad("move, turn, rewards and pickup_radius must be finite (radius >= 0)");
   if (std::fabs(c.move) >= 1.f) return bad("|move| must be below one tile");
+  if (c.shade_levels < 0 || c.shade_levels > kMaxShadeLevels) return bad("shade_levels must be in 0..16");
+  if (c.shade_levels > 0 && !(c.shade_dist > 0.f && std::isfinite(c.shade_dist)))
+    return bad("shade_dist must be finite and > 0 when shading is on");
   return true;
 }
 
@@ -96,6 +99,9 @@ DevCfg derive_cfg(const jx_env_cfg& c) {
   d.tanH = (float)std::tan((double)c.fov_deg * M_PI / 360.0);
   d.inv_tanH = (float)(1.0 / (double)d.tanH);
   d.inv_w = (float)(1.0 / (double)c.obs_w);
+  d.shade_levels = c.shade_levels;
+  d.shade_scale = c.shade_levels > 0 ? (float)((double)c.shade_levels / (double)c.shade_dist) : 0.f;
+  d.shade_mul = c.shade_levels > 0 ? (65536u + (uint32_t)c.shade_levels - 1u) / (uint32_t)c.shade_levels : 0u;
   return d;
 }
 

@@ -10,6 +10,7 @@ constexpr int kMaxSide = 64;     // one map row fits a 64-bit mask; one row per 
 constexpr int kMaxW = 128;       // column records per wave in LDS
 constexpr int kMaxH = 128;
 constexpr int kMaxDecor = 2;
+constexpr int kMaxShadeLevels = 16;
 constexpr uint32_t kStateMagic = 0x4A585331u;  // "JXS1"
 
 // Event bits written per env and step.
@@ -24,7 +25,9 @@ enum Mode : int32_t { MODE_STEP = 0, MODE_RESET = 1, MODE_RENDER = 2 };
 struct DevCfg {
   int32_t side, n_colors, key_door, goal_sprite;
   int32_t max_decor, obs_h, obs_w, n_actions;
-  int32_t cap, pad0, pad1, pad2;
+  int32_t cap, shade_levels;
+  float shade_scale;   // shade_levels / shade_dist, rounded to float
+  uint32_t shade_mul;  // ceil(2^16 / shade_levels): x / S == (x * shade_mul) >> 16 for x < 4096
   float move, turn, pr2, r_goal;
   float r_key, tanH, inv_tanH, inv_w;  // 1/tanH and 1/obs_w, rounded to float
 };

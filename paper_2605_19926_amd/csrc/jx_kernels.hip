@@ -318,7 +318,7 @@ struct ColDbg {
 __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int lane, uint8_t* lmap,
                                uint32_t* lcol, float x, float y, float sn, float cs, int goal,
                                int door, int key, uint32_t fl, int nd, int dec0, int dec1) {
-  const int N = cf.side, H = cf.obs_h, W = cf.obs_w, K = cf.n_colors;
+  const int N = cf.side, H = cf.obs_h, W = cf.obs_w, K = cf.n_colors, S_lv = cf.shade_levels;
   // the shut locked door blocks rays like a wall (tile id `shut`, -1 if none)
   const int shut = (door >= 0 && !(fl & FL_DOOR_OPEN)) ? door : -1;
   const float tanH = cf.tanH;
@@ -424,6 +424,17 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
     }
     uint32_t wc = (cell == 2) ? kDoor : kPalette[(hit < 0 ? 0 : hit) % K];
     if (side) wc = (wc >> 1) & 0x7F7F7Fu;
+    if (S_lv > 0) {
+      // distance shading: level l = min(floor(t* S / D), S - 1), each channel
+      // scaled by (S - l) / S and rounded down; the division by S (numerators
+      // below 4096) is a multiply by ceil(2^16 / S) and a shift
+      const int lv = min((int)floorf(tst * cf.shade_scale), S_lv - 1);
+      const uint32_t f = (uint32_t)(S_lv - lv), m = cf.shade_mul;
+      const uint32_t r = ((wc & 0xFFu) * f * m) >> 16;
+      const uint32_t g = (((wc >> 8) & 0xFFu) * f * m) >> 16;
+      const uint32_t b = (((wc >> 16) & 0xFFu) * f * m) >> 16;
+      wc = r | (g << 8) | (b << 16);
+    }
     const float hh = halfH * __builtin_amdgcn_rcpf(tst);
     const uint32_t wcount = (uint32_t)fminf(fmaxf(ceilf(hh - 0.5f), 0.f), halfH);
     // nearest covering sprite; on equal depth the later slot wins (painted last)

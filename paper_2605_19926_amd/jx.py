@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjx.so")
 
 JX_OK, JX_EINVAL, JX_ENOMEM, JX_EDEVICE, JX_ESTATE, JX_EBUSY = 0, -1, -2, -3, -4, -5
+ABI_VERSION = 2  # the jx_env_cfg layout this binding marshals
 JX_FORM_PLAIN, JX_FORM_PERSISTENT, JX_FORM_PIPELINE = 0, 1, 2
 JX_ROLLOUT_GRAPH, JX_ROLLOUT_FUSED = 1, 2
 JX_SERVE_COALESCE, JX_SERVE_PLAIN = 0, 1
@@ -40,7 +41,8 @@ class jx_env_cfg(ctypes.Structure):
                 ("fov_deg", ctypes.c_float), ("n_actions", ctypes.c_int32),
                 ("episode_cap", ctypes.c_int32), ("move", ctypes.c_float),
                 ("turn", ctypes.c_float), ("pickup_radius", ctypes.c_float),
-                ("r_goal", ctypes.c_float), ("r_key", ctypes.c_float)]
+                ("r_goal", ctypes.c_float), ("r_key", ctypes.c_float),
+                ("shade_levels", ctypes.c_int32), ("shade_dist", ctypes.c_float)]
 
 
 class jx_launch(ctypes.Structure):
@@ -120,10 +122,13 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             if not hasattr(L, name):
-                continue
+                raise ImportError(f"{LIB_PATH} lacks {name}: rebuild it")
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        if L.jx_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {L.jx_abi_version()}, this binding "
+                              f"expects {ABI_VERSION}: rebuild it")
         _lib = L
     return _lib
 

@@ -85,6 +85,29 @@ def test_fused_rollout_long_and_resets():
                                                         store_mode=0))])
 
 
+def test_shaded_fused_rollout_equals_graph_and_differs_from_unshaded():
+    """Distance shading through the fused and the graph rollout: bit-identical
+    to each other; walls darker than without shading, nothing else changed."""
+    import torch
+    base = W.env_cfg(side=16, loop_frac=0.1, goal_sprite=1, obs_h=64, obs_w=64, episode_cap=40)
+    shaded = dict(base, shade_levels=6, shade_dist=9.0)
+    seeds = W.seeds(31, 96)
+    acts = W.actions(31, 70, 96, 6)
+    out = {}
+    for name, cfg, form in (("fused", shaded, "fused"), ("graph", shaded, "graph"),
+                            ("plain", base, "fused")):
+        env = U.env_of(cfg, seeds, obs=False)
+        out[name] = _run(env, torch.from_numpy(acts).to(env.dev), 70, form, torch)
+        env.close()
+    for k in range(4):
+        assert np.array_equal(out["fused"][k], out["graph"][k])
+    assert np.array_equal(out["fused"][1], out["plain"][1])      # rewards unchanged
+    assert np.array_equal(out["fused"][2], out["plain"][2])      # dones unchanged
+    a = out["fused"][0].astype(np.int32)
+    b = out["plain"][0].astype(np.int32)
+    assert (a <= b).all() and (a < b).any()                      # only darker
+
+
 def test_graph_replays_agree_with_eager():
     """A captured rollout replayed several times (with eager work and syncs in
     between) equals the same steps launched one by one."""

@@ -182,6 +182,15 @@ def test_render_shared_state(wl, n, n_check):
     _render_case(wl["cfg"], n, wl["number"], n_check)
 
 
+@pytest.mark.parametrize("wl,n,n_check,levels,dist", [(W.SCALE, 4096, 256, 8, 12.0),
+                                                        (W.KEYDOOR, 8192, 160, 4, 20.0),
+                                                        (W.TINY, 16, 16, 16, 3.0)])
+def test_render_shared_state_distance_shading(wl, n, n_check, levels, dist):
+    cfg = dict(wl["cfg"], shade_levels=levels, shade_dist=dist)
+    stats = _render_case(cfg, n, wl["number"], n_check, seed_rng=41)
+    assert stats.cols >= n_check * cfg["obs_w"]
+
+
 def test_one_step_tiny_all_envs():
     for k in range(8):
         _one_step_case(W.TINY["cfg"], 16, W.TINY["number"], 16, seed_rng=100 + k)
