@@ -26,6 +26,8 @@ _LIB = os.path.join(_HERE, "libjxoracle.so")
 
 EV_BLOCKED_X, EV_BLOCKED_Y, EV_KEY, EV_GOAL = 0x01, 0x02, 0x04, 0x08
 EV_TRUNC, EV_INVALID, EV_RESET = 0x10, 0x20, 0x40
+EV_DOOR = 0x80
+TILE_DOOR, TILE_SPAWN, TILE_GOAL = 0x80, 0x20, 0x40
 SF_MOVE, SF_KEY, SF_GOAL = 0x01, 0x02, 0x04
 CF_DDA, CF_SPAN, CF_SPRITE, CF_MULTI, CF_SHADE = 0x01, 0x02, 0x04, 0x08, 0x10
 MAX_DECOR = 2
@@ -50,7 +52,8 @@ class OrcCfg(ctypes.Structure):
                 ("episode_cap", ctypes.c_int32), ("move", ctypes.c_double),
                 ("turn", ctypes.c_double), ("pickup_radius", ctypes.c_double),
                 ("r_goal", ctypes.c_double), ("r_key", ctypes.c_double),
-                ("shade_levels", ctypes.c_int32), ("shade_dist", ctypes.c_double)]
+                ("shade_levels", ctypes.c_int32), ("shade_dist", ctypes.c_double),
+                ("ascii_map", ctypes.c_char_p)]
 
 
 class OrcState(ctypes.Structure):
@@ -58,13 +61,17 @@ class OrcState(ctypes.Structure):
                 ("t", ctypes.c_int32), ("episode", ctypes.c_int32),
                 ("goal", ctypes.c_int32), ("door", ctypes.c_int32), ("key", ctypes.c_int32),
                 ("key_taken", ctypes.c_int32), ("door_open", ctypes.c_int32),
-                ("n_decor", ctypes.c_int32), ("decor", ctypes.c_int32 * MAX_DECOR)]
+                ("n_decor", ctypes.c_int32), ("decor", ctypes.c_int32 * MAX_DECOR),
+                ("akey", ctypes.c_int32 * 3), ("akey_taken", ctypes.c_int32),
+                ("doors_open", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"x": self.x, "y": self.y, "theta": self.theta, "t": self.t,
                 "episode": self.episode, "goal": self.goal, "door": self.door,
                 "key": self.key, "key_taken": self.key_taken, "door_open": self.door_open,
-                "n_decor": self.n_decor, "decor": list(self.decor)}
+                "n_decor": self.n_decor, "decor": list(self.decor),
+                "akey": list(self.akey), "akey_taken": self.akey_taken,
+                "doors_open": self.doors_open}
 
 
 _FLOAT_FIELDS = ("loop_frac", "fov_deg", "move", "turn", "pickup_radius", "r_goal", "r_key",
@@ -75,6 +82,10 @@ def make_cfg(d: dict) -> OrcCfg:
     """Configuration struct; float fields take the float32 value, widened exactly."""
     c = OrcCfg()
     for name, _ in OrcCfg._fields_:
+        if name == "ascii_map":
+            m = d.get("ascii_map")
+            c.ascii_map = None if m is None else m.encode("ascii")
+            continue
         v = d[name]
         if name in _FLOAT_FIELDS:
             setattr(c, name, float(np.float32(v)))
@@ -92,6 +103,11 @@ def state_from(d: dict) -> OrcState:
     dec = list(d.get("decor", [-1] * MAX_DECOR)) + [-1] * MAX_DECOR
     for j in range(MAX_DECOR):
         s.decor[j] = int(dec[j])
+    ak = list(d.get("akey", [-1, -1, -1]))
+    for c in range(3):
+        s.akey[c] = int(ak[c])
+    s.akey_taken = int(d.get("akey_taken", 0))
+    s.doors_open = int(d.get("doors_open", 0))
     return s
 
 
@@ -131,6 +147,8 @@ def lib():
                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, i32p, f64p, i32p]
         L.orc_cast.restype = ctypes.c_int32
+        L.orc_ascii.argtypes = [ctypes.c_char_p, ctypes.c_int32, u8p, ctypes.POINTER(ctypes.c_int32)]
+        L.orc_ascii.restype = ctypes.c_int32
         L.orc_rollout.argtypes = [ctypes.POINTER(OrcCfg), ctypes.c_int32, u64p, ctypes.c_int32,
                                   u8p, u8p]
         L.orc_rollout.restype = ctypes.c_int64
@@ -166,6 +184,25 @@ def maze(seed: int, side: int, loop_frac: float) -> np.ndarray:
     if k < 0:
         raise ValueError("bad maze arguments")
     return g
+
+
+def ascii_layout(text: str, side: int):
+    """(grid [side, side] tile bytes, keys (r, b, y tile ids, -1 absent), doors)
+    of an ASCII map; raises ValueError with the parser's code on error."""
+    g = np.zeros((side, side), np.uint8)
+    k = (ctypes.c_int32 * 3)()
+    n = lib().orc_ascii(text.encode("ascii"), side, _p(g, ctypes.c_uint8), k)
+    if n < 0:
+        raise ValueError(f"ascii map rejected ({n})")
+    return g, list(k), n
+
+
+def layout(cfg: dict, seed: int) -> np.ndarray:
+    """The env's tile grid: its ASCII map when the configuration has one, else
+    the seeded maze."""
+    if cfg.get("ascii_map") is not None:
+        return ascii_layout(cfg["ascii_map"], cfg["side"])[0]
+    return maze(seed, cfg["side"], cfg["loop_frac"])
 
 
 def maze_loops(seed: int, side: int, loop_frac: float) -> int:

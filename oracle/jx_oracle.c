@@ -135,6 +135,74 @@ static void bfs(const uint8_t* pass, int32_t N, int32_t src, int32_t* dist) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* ASCII map front-end (Table 2 symbols).  Reading: the text's rows          */
+/* (separated by '\n'; a '\r' is ignored) sit at the top-left of the N x N  */
+/* grid and every tile the text does not cover is a default wall.  '#'       */
+/* default wall; '1'..'9' coloured walls; '.' and ' ' floor; 'S' a spawn     */
+/* candidate and 'G' a goal candidate (both floor); 'r', 'b', 'y' a red,     */
+/* blue, yellow key lying on a floor tile (at most one per colour); '"' and  */
+/* '\' blue and yellow unlocked doors; 'R', 'B', 'Y' red, blue and yellow    */
+/* locked doors.  Doors are indexed in row-major order, at most 16.          */
+/* Returns the number of doors, or -1 bad arguments, -2 unknown symbol, -3   */
+/* text larger than N x N, -4 more than 16 doors, -5 a key colour twice,     */
+/* -6 no floor tile.                                                         */
+/* ------------------------------------------------------------------------ */
+int32_t orc_ascii(const char* text, int32_t N, uint8_t* grid, int32_t* keys3) {
+  if (!text || !grid || !keys3 || N < 5 || N > ORC_MAX_SIDE) return -1;
+  for (int32_t i = 0; i < N * N; ++i) grid[i] = 1;
+  keys3[0] = keys3[1] = keys3[2] = -1;
+  int32_t x = 0, y = 0, doors = 0, floors = 0;
+  for (const char* p = text; *p; ++p) {
+    const char ch = *p;
+    if (ch == '\n') {
+      ++y;
+      x = 0;
+      continue;
+    }
+    if (ch == '\r') continue;
+    if (x >= N || y >= N) return -3;
+    const int32_t id = y * N + x;
+    uint8_t v;
+    if (ch == '#') {
+      v = 1;
+    } else if (ch >= '1' && ch <= '9') {
+      v = (uint8_t)(2 + (ch - '1'));
+    } else if (ch == '.' || ch == ' ') {
+      v = 0;
+    } else if (ch == 'S') {
+      v = ORC_TILE_SPAWN;
+    } else if (ch == 'G') {
+      v = ORC_TILE_GOAL;
+    } else if (ch == 'r' || ch == 'b' || ch == 'y') {
+      const int32_t c = ch == 'r' ? 0 : (ch == 'b' ? 1 : 2);
+      if (keys3[c] >= 0) return -5;
+      keys3[c] = id;
+      v = 0;
+    } else if (ch == '"' || ch == '\\' || ch == 'R' || ch == 'B' || ch == 'Y') {
+      if (doors >= ORC_MAX_DOORS) return -4;
+      int32_t type;
+      if (ch == 'R') type = ORC_DOOR_RED_LOCKED;
+      else if (ch == 'B') type = ORC_DOOR_BLUE_LOCKED;
+      else if (ch == 'Y') type = ORC_DOOR_YELLOW_LOCKED;
+      else if (ch == '"') type = ORC_DOOR_BLUE_UNLOCKED;
+      else type = ORC_DOOR_YELLOW_UNLOCKED;
+      v = (uint8_t)(ORC_TILE_DOOR | (type << 4) | doors);
+      ++doors;
+    } else {
+      return -2;
+    }
+    if ((v & 0x8F) == 0) ++floors;
+    grid[id] = v;
+    ++x;
+  }
+  if (floors == 0) return -6;
+  return doors;
+}
+
+/* floor tile: neither a wall class nor a door (spawn/goal marks allowed) */
+static int is_floor(uint8_t v) { return (v & 0x8F) == 0; }
+
+/* ------------------------------------------------------------------------ */
 /* Episode reset.  The paper's tasks (Table 1, Table 2) have spawn and goal  */
 /* candidates and keys/locked doors; for the synthetic mazes the readings    */
 /* are, with the episode stream s = seed XOR mix64(episode + 1), drawn in    */
@@ -152,6 +220,67 @@ static void bfs(const uint8_t* pass, int32_t N, int32_t src, int32_t* dist) {
 /*     draw(remaining)-th of the remaining free tiles other than spawn, goal, */
 /*     key and door, in row-major order                                       */
 /* ------------------------------------------------------------------------ */
+/* Episode reset on an ASCII map.  Reading, with the same episode stream and  */
+/* draw order as the generated mazes: 1. spawn = the draw(|S|)-th spawn       */
+/* candidate (row-major), or free[draw(n_free)] when the map has none;        */
+/* 2. heading as for the mazes; 3. goal = the draw(|G|)-th goal candidate, or */
+/* the tile farthest from the spawn by BFS (doors passable, smallest id on    */
+/* ties) when the map has none.  Keys lie where the map puts them, all doors  */
+/* start shut.                                                                */
+static int32_t ascii_reset(const uint8_t* grid, const orc_cfg* cfg, uint64_t* s,
+                           const int32_t* freel, int32_t n_free, orc_state* out) {
+  const int32_t N = cfg->side;
+  int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * (size_t)N * N);
+  int32_t nc = 0;
+  for (int32_t id = 0; id < N * N; ++id)
+    if (is_floor(grid[id]) && (grid[id] & ORC_TILE_SPAWN)) cand[nc++] = id;
+  const int32_t spawn = nc > 0 ? cand[orc_rng_range(s, (uint32_t)nc)]
+                               : freel[orc_rng_range(s, (uint32_t)n_free)];
+  const uint32_t k24 = (uint32_t)(orc_rng_next(s) >> 40);
+  const float two_pi_f = (float)(2.0 * M_PI);
+  const float step_f = two_pi_f * 0x1p-24f;
+  const float th_f = (float)k24 * step_f;
+  nc = 0;
+  for (int32_t id = 0; id < N * N; ++id)
+    if (is_floor(grid[id]) && (grid[id] & ORC_TILE_GOAL)) cand[nc++] = id;
+  int32_t goal;
+  if (nc > 0) {
+    goal = cand[orc_rng_range(s, (uint32_t)nc)];
+  } else {
+    uint8_t* pass = (uint8_t*)calloc((size_t)N * N, 1);
+    int32_t* ds = (int32_t*)malloc(sizeof(int32_t) * (size_t)N * N);
+    for (int32_t id = 0; id < N * N; ++id) pass[id] = is_floor(grid[id]) || (grid[id] & ORC_TILE_DOOR);
+    bfs(pass, N, spawn, ds);
+    int32_t L = 0;
+    goal = spawn;
+    for (int32_t id = 0; id < N * N; ++id)
+      if (ds[id] > L) { L = ds[id]; goal = id; }
+    free(pass);
+    free(ds);
+  }
+  free(cand);
+  uint8_t* tmp = (uint8_t*)malloc((size_t)N * N);
+  int32_t keys3[3];
+  const int32_t nd = orc_ascii(cfg->ascii_map, N, tmp, keys3);
+  free(tmp);
+  if (nd < 0) return -1;
+  out->x = (double)(spawn % N) + 0.5;
+  out->y = (double)(spawn / N) + 0.5;
+  out->theta = (double)th_f;
+  out->t = 0;
+  out->goal = goal;
+  out->door = -1;
+  out->key = -1;
+  out->n_decor = 0;
+  out->decor[0] = out->decor[1] = -1;
+  out->akey[0] = keys3[0];
+  out->akey[1] = keys3[1];
+  out->akey[2] = keys3[2];
+  out->akey_taken = 0;
+  out->doors_open = 0;
+  return 0;
+}
+
 int32_t orc_reset(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, int32_t episode,
                   orc_state* out) {
   if (!grid || !cfg || !out) return -1;
@@ -162,10 +291,18 @@ int32_t orc_reset(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, int32_
   int32_t* freel = (int32_t*)malloc(sizeof(int32_t) * (size_t)N * N);
   int32_t n_free = 0;
   for (int32_t id = 0; id < N * N; ++id)
-    if (grid[id] == 0) freel[n_free++] = id;
+    if (is_floor(grid[id])) freel[n_free++] = id;
   if (n_free == 0) { free(freel); return -1; }
 
   memset(out, 0, sizeof(*out));
+  out->akey[0] = out->akey[1] = out->akey[2] = -1;
+  if (cfg->ascii_map) {
+    int32_t rc = ascii_reset(grid, cfg, &s, freel, n_free, out);
+    free(freel);
+    if (rc) return rc;
+    out->episode = episode;
+    return 0;
+  }
   int32_t spawn = freel[orc_rng_range(&s, (uint32_t)n_free)];
   uint32_t k24 = (uint32_t)(orc_rng_next(&s) >> 40);
   const float two_pi_f = (float)(2.0 * M_PI);
@@ -174,7 +311,7 @@ int32_t orc_reset(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, int32_
 
   uint8_t* pass = (uint8_t*)malloc((size_t)N * N);
   int32_t* ds = (int32_t*)malloc(sizeof(int32_t) * (size_t)N * N);
-  for (int32_t id = 0; id < N * N; ++id) pass[id] = (grid[id] == 0);
+  for (int32_t id = 0; id < N * N; ++id) pass[id] = is_floor(grid[id]);
   bfs(pass, N, spawn, ds);
   int32_t L = 0, goal = spawn;
   for (int32_t id = 0; id < N * N; ++id)
@@ -247,15 +384,28 @@ int32_t orc_reset(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, int32_
   return 0;
 }
 
-/* Tile (tx, ty) blocks movement or rays: outside the grid, a wall, or the   */
-/* locked door while it is shut (Table 2: locked doors; Table 1: key-door).   */
-static int blocks(const uint8_t* grid, int32_t N, int32_t door, int32_t door_open, int32_t tx,
-                  int32_t ty) {
+/* Tile (tx, ty) blocks movement or rays: outside the grid, a wall, a door of */
+/* the map that is not open (`doors`: bit = door index), or the generated    */
+/* maze's locked door while it is shut (Table 2: doors; Table 1: key-door).   */
+static int blocks(const uint8_t* grid, int32_t N, int32_t door, int32_t door_open, int32_t doors,
+                  int32_t tx, int32_t ty) {
   if (tx < 0 || ty < 0 || tx >= N || ty >= N) return 1;
-  int32_t id = ty * N + tx;
-  if (grid[id] != 0) return 1;
+  const int32_t id = ty * N + tx;
+  const uint8_t v = grid[id];
+  if (v & ORC_TILE_DOOR) return !((doors >> (v & 15)) & 1);
+  if (v & 0x0F) return 1;
   if (id == door && !door_open) return 1;
   return 0;
+}
+
+/* Bit mask of the map's locked doors of colour c (0 red, 1 blue, 2 yellow). */
+static int32_t locked_doors_of(const uint8_t* grid, int32_t N, int32_t c) {
+  int32_t m = 0;
+  for (int32_t id = 0; id < N * N; ++id) {
+    const uint8_t v = grid[id];
+    if ((v & ORC_TILE_DOOR) && ((v >> 4) & 7) == c) m |= 1 << (v & 15);
+  }
+  return m;
 }
 
 static int near_int(double v, double w) { return fabs(v - floor(v + 0.5)) <= w; }
@@ -309,31 +459,56 @@ int32_t orc_step_w(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, const
 
   const int32_t door = in->door;
   const int32_t dopen = in->door_open;
+  int32_t doors = in->doors_open;
   double x = in->x, y = in->y;
+  /* Table 2 unlocked doors open when the agent walks into them; that move is
+   * refused (reading) */
+#define BUMP(tx_, ty_)                                                             \
+  do {                                                                             \
+    const int32_t bx = (tx_), by = (ty_);                                          \
+    if (bx >= 0 && by >= 0 && bx < N && by < N) {                                  \
+      const uint8_t bv = grid[by * N + bx];                                        \
+      const int32_t bt = (bv >> 4) & 7;                                            \
+      if ((bv & ORC_TILE_DOOR) && (bt == ORC_DOOR_BLUE_UNLOCKED || bt == ORC_DOOR_YELLOW_UNLOCKED) && \
+          !((doors >> (bv & 15)) & 1)) {                                           \
+        doors |= 1 << (bv & 15);                                                   \
+        ev |= ORC_EV_DOOR;                                                         \
+      }                                                                            \
+    }                                                                              \
+  } while (0)
   if (mx != 0.0) {
     double nx = x + mx;
     int32_t fy = (int32_t)floor(y);
     if (near_int(nx, W5)) {
       int32_t k = (int32_t)floor(nx + 0.5);
-      if (blocks(grid, N, door, dopen, k - 1, fy) != blocks(grid, N, door, dopen, k, fy)) sf |= ORC_SF_MOVE;
+      if (blocks(grid, N, door, dopen, doors, k - 1, fy) != blocks(grid, N, door, dopen, doors, k, fy)) sf |= ORC_SF_MOVE;
     }
-    if (!blocks(grid, N, door, dopen, (int32_t)floor(nx), fy)) x = nx;
-    else ev |= ORC_EV_BLOCKED_X;
+    if (!blocks(grid, N, door, dopen, doors, (int32_t)floor(nx), fy)) {
+      x = nx;
+    } else {
+      ev |= ORC_EV_BLOCKED_X;
+      BUMP((int32_t)floor(nx), fy);
+    }
   }
   if (my != 0.0) {
     double ny = y + my;
     int32_t fx = (int32_t)floor(x);
     if (near_int(ny, W5)) {
       int32_t k = (int32_t)floor(ny + 0.5);
-      if (blocks(grid, N, door, dopen, fx, k - 1) != blocks(grid, N, door, dopen, fx, k)) sf |= ORC_SF_MOVE;
+      if (blocks(grid, N, door, dopen, doors, fx, k - 1) != blocks(grid, N, door, dopen, doors, fx, k)) sf |= ORC_SF_MOVE;
     }
     if (near_int(x, W5)) {
       int32_t k = (int32_t)floor(x + 0.5), fny = (int32_t)floor(ny);
-      if (blocks(grid, N, door, dopen, k - 1, fny) != blocks(grid, N, door, dopen, k, fny)) sf |= ORC_SF_MOVE;
+      if (blocks(grid, N, door, dopen, doors, k - 1, fny) != blocks(grid, N, door, dopen, doors, k, fny)) sf |= ORC_SF_MOVE;
     }
-    if (!blocks(grid, N, door, dopen, fx, (int32_t)floor(ny))) y = ny;
-    else ev |= ORC_EV_BLOCKED_Y;
+    if (!blocks(grid, N, door, dopen, doors, fx, (int32_t)floor(ny))) {
+      y = ny;
+    } else {
+      ev |= ORC_EV_BLOCKED_Y;
+      BUMP(fx, (int32_t)floor(ny));
+    }
   }
+#undef BUMP
 
   int32_t key_taken = in->key_taken, door_open = in->door_open;
   if (in->key >= 0 && !key_taken) {
@@ -346,6 +521,24 @@ int32_t orc_step_w(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, const
       door_open = 1;
       r += cfg->r_key;
       ev |= ORC_EV_KEY;
+    }
+  }
+  /* Table 2 keys: picking up the key of colour c opens every locked door of
+   * colour c (reward r_key each) */
+  int32_t ataken = in->akey_taken;
+  for (int32_t c = 0; c < 3; ++c) {
+    if (in->akey[c] < 0 || ((ataken >> c) & 1)) continue;
+    double kx = (double)(in->akey[c] % N) + 0.5, ky = (double)(in->akey[c] / N) + 0.5;
+    double d2 = (x - kx) * (x - kx) + (y - ky) * (y - ky);
+    double r2 = cfg->pickup_radius * cfg->pickup_radius;
+    if (fabs(d2 - r2) <= W5) sf |= ORC_SF_KEY;
+    if (d2 < r2) {
+      ataken |= 1 << c;
+      r += cfg->r_key;
+      ev |= ORC_EV_KEY;
+      const int32_t m = locked_doors_of(grid, N, c);
+      if (m & ~doors) ev |= ORC_EV_DOOR;
+      doors |= m;
     }
   }
   int32_t term = 0;
@@ -376,6 +569,8 @@ int32_t orc_step_w(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed, const
     out->t = t2;
     out->key_taken = key_taken;
     out->door_open = door_open;
+    out->akey_taken = ataken;
+    out->doors_open = doors;
   }
   if (reward) *reward = r;
   if (done) *done = d;
@@ -406,8 +601,8 @@ typedef struct {
   int32_t n_ties, first_tie;
 } cast_out;
 
-static void cast_walk(const uint8_t* grid, int32_t N, int32_t door, int32_t door_open, double x,
-                      double y, double rx, double ry, int32_t flip_at, cast_out* o) {
+static void cast_walk(const uint8_t* grid, int32_t N, int32_t door, int32_t door_open, int32_t doors,
+                      double x, double y, double rx, double ry, int32_t flip_at, cast_out* o) {
   int32_t ix = (int32_t)floor(x), iy = (int32_t)floor(y);
   int32_t sx = rx > 0 ? 1 : -1, sy = ry > 0 ? 1 : -1;
   double X0 = rx > 0 ? ix + 1 : ix, Y0 = ry > 0 ? iy + 1 : iy;
@@ -424,9 +619,9 @@ static void cast_walk(const uint8_t* grid, int32_t N, int32_t door, int32_t door
     if (isfinite(tx) && isfinite(ty)) {
       double big = tx > ty ? tx : ty;
       if (fabs(tx - ty) <= 1e-5 * big) {
-        if (blocks(grid, N, door, door_open, ix + sx, iy) ||
-            blocks(grid, N, door, door_open, ix, iy + sy) ||
-            blocks(grid, N, door, door_open, ix + sx, iy + sy)) {
+        if (blocks(grid, N, door, door_open, doors, ix + sx, iy) ||
+            blocks(grid, N, door, door_open, doors, ix, iy + sy) ||
+            blocks(grid, N, door, door_open, doors, ix + sx, iy + sy)) {
           if (o->n_ties == 0) o->first_tie = cmp;
           o->n_ties += 1;
         }
@@ -437,7 +632,7 @@ static void cast_walk(const uint8_t* grid, int32_t N, int32_t door, int32_t door
     int32_t sd;
     if (step_x) { ix += sx; kx += 1; tc = tx; sd = 0; }
     else { iy += sy; ky += 1; tc = ty; sd = 1; }
-    if (blocks(grid, N, door, door_open, ix, iy)) {
+    if (blocks(grid, N, door, door_open, doors, ix, iy)) {
       o->hit = (ix >= 0 && iy >= 0 && ix < N && iy < N) ? iy * N + ix : -1;
       o->side = sd;
       o->t = tc;
@@ -449,7 +644,7 @@ static void cast_walk(const uint8_t* grid, int32_t N, int32_t door, int32_t door
 int32_t orc_cast(const uint8_t* grid, int32_t N, int32_t door, int32_t door_open, double x,
                  double y, double rx, double ry, int32_t* side, double* tstar, int32_t* flags) {
   cast_out o;
-  cast_walk(grid, N, door, door_open, x, y, rx, ry, -1, &o);
+  cast_walk(grid, N, door, door_open, 0, x, y, rx, ry, -1, &o);
   if (side) *side = o.side;
   if (tstar) *tstar = o.t;
   if (flags) *flags = (o.n_ties > 0 ? ORC_CF_DDA : 0) | (o.n_ties > 1 ? ORC_CF_MULTI : 0);
@@ -465,6 +660,13 @@ static const uint8_t kDoor[3] = {120, 0, 0};
 static const uint8_t kKeyCol[3] = {255, 40, 40};
 static const uint8_t kGoalCol[3] = {255, 230, 0};
 static const uint8_t kDecorCol[3] = {0, 200, 120};
+/* ASCII maps: walls '1'..'9', doors by type, keys by colour */
+static const uint8_t kWall9[9][3] = {{180, 40, 40},  {40, 160, 40},  {40, 60, 180},
+                                     {190, 170, 40}, {150, 40, 170}, {40, 160, 170},
+                                     {200, 110, 30}, {150, 150, 150}, {230, 230, 230}};
+static const uint8_t kDoorCol[5][3] = {{120, 0, 0},   {0, 30, 130},  {140, 120, 0},
+                                       {70, 110, 230}, {230, 200, 60}};
+static const uint8_t kAKeyCol[3][3] = {{255, 40, 40}, {40, 110, 255}, {255, 200, 40}};
 
 /* ------------------------------------------------------------------------ */
 /* Frame.  Camera reading: horizontal FOV with tanH = tan(fov/2); column c   */
@@ -504,7 +706,7 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
     double rx = dirx + camX * tanH * rgtx;
     double ry = diry + camX * tanH * rgty;
     cast_out o;
-    cast_walk(grid, N, door, dopen, st->x, st->y, rx, ry, -1, &o);
+    cast_walk(grid, N, door, dopen, st->doors_open, st->x, st->y, rx, ry, -1, &o);
     if (o.n_ties > 0) fl[col] |= ORC_CF_DDA;
     if (o.n_ties > 1) fl[col] |= ORC_CF_MULTI;
     if (alt_hit || alt_side || alt_t) {
@@ -512,7 +714,7 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
       double at = 0.0;
       if (o.n_ties > 0) {
         cast_out a;
-        cast_walk(grid, N, door, dopen, st->x, st->y, rx, ry, o.first_tie, &a);
+        cast_walk(grid, N, door, dopen, st->doors_open, st->x, st->y, rx, ry, o.first_tie, &a);
         ah = a.hit;
         as = a.side;
         at = a.t;
@@ -527,7 +729,12 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
     if (tstar) tstar[col] = o.t;
 
     uint8_t wc[3];
-    const uint8_t* base = (o.hit == door && !dopen) ? kDoor : kPal[(o.hit < 0 ? 0 : o.hit) % K];
+    const uint8_t hv = o.hit >= 0 ? grid[o.hit] : 1;
+    const uint8_t* base;
+    if (o.hit == door && !dopen) base = kDoor;
+    else if (hv & ORC_TILE_DOOR) base = kDoorCol[(hv >> 4) & 7];
+    else if ((hv & 0x0F) >= 2) base = kWall9[(hv & 0x0F) - 2];
+    else base = kPal[(o.hit < 0 ? 0 : o.hit) % K];
     for (int32_t ch = 0; ch < 3; ++ch) wc[ch] = o.side ? (uint8_t)(base[ch] >> 1) : base[ch];
     if (cfg->shade_levels > 0) {
       /* Distance shading (the ray-casting section lets the wall colour depend
@@ -559,9 +766,14 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
   }
 
   /* sprites */
-  int32_t sid[2 + ORC_MAX_DECOR];
-  const uint8_t* scol[2 + ORC_MAX_DECOR];
+  int32_t sid[8];
+  const uint8_t* scol[8];
   int32_t ns = 0;
+  if (cfg->ascii_map) {
+    /* keys not yet taken in colour order, then the goal */
+    for (int32_t c = 0; c < 3; ++c)
+      if (st->akey[c] >= 0 && !((st->akey_taken >> c) & 1)) { sid[ns] = st->akey[c]; scol[ns] = kAKeyCol[c]; ++ns; }
+  }
   if (st->key >= 0 && !st->key_taken) { sid[ns] = st->key; scol[ns] = kKeyCol; ++ns; }
   if (cfg->goal_sprite && st->goal >= 0) { sid[ns] = st->goal; scol[ns] = kGoalCol; ++ns; }
   for (int32_t j = 0; j < st->n_decor && j < ORC_MAX_DECOR; ++j) {
@@ -569,8 +781,8 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
     scol[ns] = kDecorCol;
     ++ns;
   }
-  double tY[4], tX[4], u[4], hw[4], hs[4], dn[4];
-  int32_t vis[4];
+  double tY[8], tX[8], u[8], hw[8], hs[8], dn[8];
+  int32_t vis[8];
   for (int32_t j = 0; j < ns; ++j) {
     double cx = (sid[j] % N) + 0.5, cy = (sid[j] / N) + 0.5;
     double dx = cx - st->x, dy = cy - st->y;
@@ -587,7 +799,7 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
     }
   }
   /* painting order: descending tY, equal tY ascending index */
-  int32_t order[4];
+  int32_t order[8];
   for (int32_t j = 0; j < ns; ++j) order[j] = j;
   for (int32_t a = 0; a < ns; ++a)
     for (int32_t b = a + 1; b < ns; ++b) {
@@ -651,7 +863,10 @@ int64_t orc_rollout(const orc_cfg* cfg, int32_t n_envs, const uint64_t* seeds, i
   uint8_t* obs = (uint8_t*)malloc(fb);
   int64_t done_steps = 0;
   for (int32_t i = 0; i < n_envs; ++i) {
-    if (orc_maze(seeds[i], N, cfg->loop_frac, grid) < 0) break;
+    int32_t keys3[3];
+    if (cfg->ascii_map ? orc_ascii(cfg->ascii_map, N, grid, keys3) < 0
+                       : orc_maze(seeds[i], N, cfg->loop_frac, grid) < 0)
+      break;
     orc_state st, nx;
     orc_reset(grid, cfg, seeds[i], 0, &st);
     for (int32_t t = 0; t < n_steps; ++t) {

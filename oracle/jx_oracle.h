@@ -47,6 +47,7 @@ typedef struct {
   double move, turn, pickup_radius, r_goal, r_key;
   int32_t shade_levels;  /* S: distance-shading levels, 0 = off */
   double shade_dist;     /* D: distance at which the last level starts */
+  const char* ascii_map; /* NULL: generated maze; else an ASCII map (Table 2 symbols) */
 } orc_cfg;
 
 /* Per-environment state.  Positions in tile units, heading in radians from +x
@@ -58,7 +59,26 @@ typedef struct {
   int32_t key_taken, door_open;
   int32_t n_decor;
   int32_t decor[ORC_MAX_DECOR];
+  /* ASCII maps: tiles of the red, blue and yellow keys (-1 absent), the keys
+   * taken (bit c), and the doors open (bit = door index) */
+  int32_t akey[3];
+  int32_t akey_taken;
+  int32_t doors_open;
 } orc_state;
+
+/* Tile bytes of a grid.  0 floor; low nibble 1 = default wall ('#', colour
+ * palette[id mod K]); 2..10 = coloured wall '1'..'9'; bit 7 = door, with its
+ * type in bits 4..6 (ORC_DOOR_*) and its index (0..15) in bits 0..3.  On floor
+ * tiles bit 5 marks a spawn candidate ('S') and bit 6 a goal candidate ('G'). */
+#define ORC_TILE_DOOR   0x80
+#define ORC_TILE_SPAWN  0x20
+#define ORC_TILE_GOAL   0x40
+#define ORC_DOOR_RED_LOCKED      0
+#define ORC_DOOR_BLUE_LOCKED     1
+#define ORC_DOOR_YELLOW_LOCKED   2
+#define ORC_DOOR_BLUE_UNLOCKED   3
+#define ORC_DOOR_YELLOW_UNLOCKED 4
+#define ORC_MAX_DOORS 16
 
 /* Step event bits (identical meaning on every implementation of the rules). */
 #define ORC_EV_BLOCKED_X 0x01
@@ -68,6 +88,7 @@ typedef struct {
 #define ORC_EV_TRUNC     0x10
 #define ORC_EV_INVALID   0x20
 #define ORC_EV_RESET     0x40
+#define ORC_EV_DOOR      0x80   /* a door opened (bumped, or unlocked by a key) */
 
 /* Step decision flags: the outcome sits within 1e-5 of a decision boundary. */
 #define ORC_SF_MOVE  0x01   /* S1: collision boundary */
@@ -90,6 +111,11 @@ uint32_t orc_rng_range(uint64_t* s, uint32_t n);    /* uniform draw in [0, n) */
 /* Writes the N*N tile grid (0 floor, 1 wall) for `seed`.  Returns the number
  * of separator walls removed for loops, or -1 on bad arguments. */
 int32_t orc_maze(uint64_t seed, int32_t N, double loop_frac, uint8_t* grid);
+
+/* Parses an ASCII map (Table 2 symbols, rows separated by '\n') into the N*N
+ * grid (tile bytes above); keys3 receives the red, blue and yellow key tiles
+ * (-1 absent).  Returns the number of doors or a negative error. */
+int32_t orc_ascii(const char* text, int32_t N, uint8_t* grid, int32_t* keys3);
 
 /* ---- episodes ---------------------------------------------------------- */
 int32_t orc_reset(const uint8_t* grid, const orc_cfg* cfg, uint64_t seed,

@@ -27,7 +27,7 @@ def env_cfg(**kw) -> dict:
     base = dict(side=16, n_colors=8, loop_frac=0.0, key_door=0, goal_sprite=0, max_decor=0,
                 obs_h=64, obs_w=64, fov_deg=60.0, n_actions=6, episode_cap=512, move=0.1,
                 turn=PI / 16, pickup_radius=0.3, r_goal=1.0, r_key=0.5, shade_levels=0,
-                shade_dist=8.0)
+                shade_dist=8.0, ascii_map=None)
     for k in kw:
         if k not in base:
             raise KeyError(k)
