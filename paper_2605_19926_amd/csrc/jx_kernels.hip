@@ -28,10 +28,23 @@ namespace {
 
 constexpr uint32_t rgb(uint32_t r, uint32_t g, uint32_t b) { return r | (g << 8) | (b << 16); }
 
-// Colours of this build (the paper draws flat colours without assets).
-__constant__ uint32_t kPalette[8] = {rgb(180, 40, 40), rgb(40, 160, 40),  rgb(40, 60, 180),
-                                     rgb(190, 170, 40), rgb(150, 40, 170), rgb(40, 160, 170),
-                                     rgb(200, 110, 30), rgb(150, 150, 150)};
+// Colours of this build (the paper draws flat colours without assets).  The
+// table is copied into each workgroup's LDS at kernel start: an indexed lookup
+// in LDS costs no global load, and a global load inside a step loop would
+// wait for every frame store the wave has in flight.
+constexpr int kColorWords = 32;
+constexpr int kClrPalette = 0;  // 8 wall colours, indexed by tile id mod K
+constexpr uint32_t kColorTable[kColorWords] = {
+    rgb(180, 40, 40), rgb(40, 160, 40),  rgb(40, 60, 180),  rgb(190, 170, 40),
+    rgb(150, 40, 170), rgb(40, 160, 170), rgb(200, 110, 30), rgb(150, 150, 150)};
+
+__device__ __forceinline__ void stage_colors(uint32_t* lclr) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kColorWords; ++i) lclr[i] = kColorTable[i];
+  }
+  __syncthreads();
+}
 constexpr uint32_t kCeil = rgb(50, 50, 60);
 constexpr uint32_t kFloor = rgb(90, 80, 70);
 constexpr uint32_t kDoor = rgb(120, 0, 0);
@@ -316,6 +329,7 @@ struct ColDbg {
 // writes debug records when asked).
 // sn, cs: sine and cosine of the heading.
 __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int lane, uint8_t* lmap,
+                               const uint32_t* lclr,
                                uint32_t* lcol, float x, float y, float sn, float cs, int goal,
                                int door, int key, uint32_t fl, int nd, int dec0, int dec1) {
   const int N = cf.side, H = cf.obs_h, W = cf.obs_w, K = cf.n_colors, S_lv = cf.shade_levels;
@@ -422,7 +436,7 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
         cell = (!out && sid_ == shut) ? 2 : 1;
       }
     }
-    uint32_t wc = (cell == 2) ? kDoor : kPalette[(hit < 0 ? 0 : hit) % K];
+    uint32_t wc = (cell == 2) ? kDoor : lclr[kClrPalette + (hit < 0 ? 0 : hit) % K];
     if (side) wc = (wc >> 1) & 0x7F7F7Fu;
     if (S_lv > 0) {
       // distance shading: level l = min(floor(t* S / D), S - 1), each channel
@@ -578,7 +592,7 @@ __device__ __forceinline__ void stage_map(const EnvIn<MAXN>& in, int lane, uint8
 // action < 0: read this env's action from io.act.
 template <int MAXN, bool STAGE = true>
 __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevIo& io, int action,
-                            int lane, uint8_t* lmap, uint32_t* lcol, EnvOut& o) {
+                            int lane, uint8_t* lmap, const uint32_t* lclr, uint32_t* lcol, EnvOut& o) {
   const DevCfg& cf = in.cf;
   const int env = in.env;
   const int N = cf.side;
@@ -681,8 +695,8 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   }
   if (heading_changed) sincosf(th, &sn, &cs);
   if (io.obs || io.dbg)
-    render_columns(cf, io, env, lane, lmap, lcol, x, y, sn, cs, goal, door, key, fl, nd, dec0, dec1);
-  o.obs_off = S.uniform ? (int64_t)env * S.obs_stride : S.obs_off[env];
+    render_columns(cf, io, env, lane, lmap, lclr, lcol, x, y, sn, cs, goal, door, key, fl, nd, dec0, dec1);
+  o.obs_off = 0;  // set by the caller (obs_off_of), outside any step loop
   o.env = env;
   o.W = cf.obs_w;
   o.H = cf.obs_h;
@@ -728,14 +742,20 @@ __device__ void write_back(const DevState& S, const DevIo& io, const EnvOut& o, 
   }
 }
 
+// Byte offset of env's frame in a step's observation buffer.
+__device__ __forceinline__ int64_t obs_off_of(const DevState& S, int env) {
+  return S.uniform ? (int64_t)env * S.obs_stride : S.obs_off[env];
+}
+
 // The whole per-env pipeline in one wave.
 template <int MAXN>
 __device__ __forceinline__ void process_env(const DevState& S, const DevIo& io, int env, int lane, uint8_t* lmap,
-                            uint32_t* lcol) {
+                            const uint32_t* lclr, uint32_t* lcol) {
   EnvIn<MAXN> in;
   load_env<MAXN>(S, env, lane, in);
   EnvOut o;
-  produce_env<MAXN>(in, S, io, -1, lane, lmap, lcol, o);
+  produce_env<MAXN>(in, S, io, -1, lane, lmap, lclr, lcol, o);
+  o.obs_off = obs_off_of(S, env);
   if (io.obs) fill_frame(lcol, io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
   write_back(S, io, o, lane);
 }
@@ -758,11 +778,13 @@ __global__ __launch_bounds__(64 * WPB) void k_plain(DevState S, DevIo io0, const
                                                     int t) {
   __shared__ __align__(16) uint8_t smap[WPB][MAXN * MAXN];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
+  __shared__ uint32_t sclr[kColorWords];
+  stage_colors(sclr);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int env = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + w);
   if (env >= S.n) return;
   const DevIo io = io_of(io0, rd, t);
-  process_env<MAXN>(S, io, env, lane, smap[w], scol[w]);
+  process_env<MAXN>(S, io, env, lane, smap[w], sclr, scol[w]);
 }
 
 // Work distribution of the persistent forms.  Items (positions in a work
@@ -826,12 +848,14 @@ __global__ __launch_bounds__(64 * WPB) void k_persist(DevState S, DevIo io0, con
                                                       int t, uint32_t seq) {
   __shared__ __align__(16) uint8_t smap[WPB][kMaxSide * kMaxSide];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
+  __shared__ uint32_t sclr[kColorWords];
+  stage_colors(sclr);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const DevIo io = io_of(io0, rd, t);
   const QueueView v = queue_view<WPB>(S.queues, seq, S.n, w, lane);
   queue_drain(v, lane, [&](int pos) {
     const int env = __builtin_amdgcn_readfirstlane(S.order[pos]);
-    process_env<kMaxSide>(S, io, env, lane, smap[w], scol[w]);
+    process_env<kMaxSide>(S, io, env, lane, smap[w], sclr, scol[w]);
   });
 }
 
@@ -842,6 +866,8 @@ __global__ __launch_bounds__(64 * WPB) void k_serve(const DevState* states, cons
                                                     uint32_t* queues, uint32_t seq) {
   __shared__ __align__(16) uint8_t smap[WPB][kMaxSide * kMaxSide];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
+  __shared__ uint32_t sclr[kColorWords];
+  stage_colors(sclr);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const QueueView v = queue_view<WPB>(queues, seq, n_items, w, lane);
   queue_drain(v, lane, [&](int pos) {
@@ -850,7 +876,7 @@ __global__ __launch_bounds__(64 * WPB) void k_serve(const DevState* states, cons
     // fields are read from the descriptors where they are used (scalar loads)
     const DevState& S = states[d];
     const DevIo& io = ios[d];
-    process_env<kMaxSide>(S, io, env, lane, smap[w], scol[w]);
+    process_env<kMaxSide>(S, io, env, lane, smap[w], sclr, scol[w]);
   });
 }
 
@@ -868,6 +894,8 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
   __shared__ __align__(16) uint8_t smap[P][MAXN * MAXN];
   __shared__ __align__(16) uint32_t scol[P][2][2 * kMaxW];
   __shared__ EnvOut sout[P][2];
+  __shared__ uint32_t sclr[kColorWords];
+  stage_colors(sclr);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int pair = w >> 1;
   const bool writer = (w & 1) != 0;
@@ -886,7 +914,8 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
         const int nitem = item + pairs;
         if (nitem < S.n) load_env<MAXN>(S, __builtin_amdgcn_readfirstlane(S.order[nitem]), lane, nxt);
         EnvOut o;
-        produce_env<MAXN>(cur, S, io, -1, lane, smap[pair], scol[pair][b], o);
+        produce_env<MAXN>(cur, S, io, -1, lane, smap[pair], sclr, scol[pair][b], o);
+        o.obs_off = obs_off_of(S, o.env);
         if (lane == 0) sout[pair][b] = o;
         cur = nxt;
       } else if (lane == 0) {
@@ -917,6 +946,8 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
                                                    int T, int store_mode) {
   __shared__ __align__(16) uint8_t smap[WPB][MAXN * MAXN];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
+  __shared__ uint32_t sclr[kColorWords];
+  stage_colors(sclr);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int waves = (int)gridDim.x * WPB;
   const int64_t n = S.n;
@@ -929,6 +960,7 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
     EnvIn<MAXN> in;
     load_env<MAXN>(S, env, lane, in);
     stage_map<MAXN>(in, lane, smap[w]);
+    const int64_t obs_off = obs_off_of(S, env);
     uint32_t n_invalid = 0, last_ev = 0;
     for (int t0 = 0; t0 < T; t0 += 128) {
       // lane l holds the actions of steps t0 + l and t0 + 64 + l
@@ -937,15 +969,24 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
       const uint32_t a1 = s1 < T ? act[(int64_t)s1 * n + env] : 0u;
       const int tend = T - t0 < 128 ? T - t0 : 128;
       for (int k = 0; k < tend; ++k) {
-        const int a = __shfl((int)(k < 64 ? a0 : a1), k & 63, 64);
+        // (& 0xFF: the action is a byte, so produce_env's load path for a
+        // negative action folds away and the step loop issues no load)
+        // Wait for this wave's previous frame stores before the next step: a
+        // wave then has at most one frame's stores in flight.  Measured on the
+        // 4096-env workload this bound keeps the HBM write stream more
+        // efficient than letting stores of many steps pile up (and the casting
+        // of the other waves still overlaps them).  vmcnt 0, other counters
+        // untouched.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        const int a = __shfl((int)(k < 64 ? a0 : a1), k & 63, 64) & 0xFF;
         // an opaque copy of the lane id keeps the per-column set-up inside the
         // loop instead of hoisted out of it and held live across all steps
         int ln = lane;
         asm volatile("" : "+v"(ln));
         EnvOut o;
-        produce_env<MAXN, false>(in, S, io, a, ln, smap[w], scol[w], o);
+        produce_env<MAXN, false>(in, S, io, a, ln, smap[w], sclr, scol[w], o);
         const int t = t0 + k;
-        fill_frame(scol[w], obs + (int64_t)t * obs_stride + o.obs_off, o.W, o.H, ln, store_mode);
+        fill_frame(scol[w], obs + (int64_t)t * obs_stride + obs_off, o.W, o.H, ln, store_mode);
         if (lane == 0) {
           rew[(int64_t)t * n + env] = o.reward;
           dn[(int64_t)t * n + env] = (uint8_t)o.done;
