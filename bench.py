@@ -427,29 +427,38 @@ def main() -> int:
         torch.cuda.synchronize()
         ss = s0.elapsed_time(s1) / 1e3
         single = {"steps": Ks, "env_steps_per_s": n * Ks / ss, "ms_per_step": ss / Ks * 1e3}
-    # distance-shaded walls (render option), same workload and form
-    shaded = None
-    if args.form == "fused" and slots > 1:
-        scfg = dict(cfg, shade_levels=8, shade_dist=12.0)
-        senv = jx.Env(seeds, scfg)
-        senv.reset(obs[:ob])
+    def variant_rate(vcfg, vseeds, name):
+        """Fused 128-step rollouts of a variant configuration into the same
+        frame ring (same frame size), timed like the headline."""
+        venv = jx.Env(vseeds, vcfg)
+        venv.reset(obs[:ob])
         Kv = min(K, 2560)
 
-        def srun(first, count):
+        def vrun(first, count):
             for t, slot, chunk in plan(first, count):
-                senv.rollout(acts[t:t + chunk], obs[slot * ob:], rew[slot * n:], done[slot * n:],
+                venv.rollout(acts[t:t + chunk], obs[slot * ob:], rew[slot * n:], done[slot * n:],
                              chunk, obs_stride=ob, graph=False, fused=True)
-        srun(0, Wu)
+        vrun(0, Wu)
         torch.cuda.synchronize()
         v0, v1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         v0.record(stream)
-        srun(Wu, Kv)
+        vrun(Wu, Kv)
         v1.record(stream)
         torch.cuda.synchronize()
         vs = v0.elapsed_time(v1) / 1e3
-        shaded = {"shade_levels": 8, "shade_dist": 12.0, "steps": Kv,
-                  "env_steps_per_s": n * Kv / vs, "ms_per_step": vs / Kv * 1e3}
-        senv.close()
+        venv.close()
+        progress(f"{name}: {n * Kv / vs:.4g} env-steps/s")
+        return {"steps": Kv, "env_steps_per_s": n * Kv / vs, "ms_per_step": vs / Kv * 1e3}
+
+    shaded = ascii_maps = None
+    if args.form == "fused" and slots > 1:
+        # distance-shaded walls (render option), same workload
+        shaded = dict(shade_levels=8, shade_dist=12.0,
+                      **variant_rate(dict(cfg, shade_levels=8, shade_dist=12.0), seeds, "shaded"))
+        # the 16x16 ASCII map (Table 2 symbols: keys, locked and unlocked doors,
+        # candidates), same env count and frame size
+        ascii_maps = dict(workload=W.ASCII["name"],
+                          **variant_rate(W.ASCII["cfg"], W.seeds(W.ASCII["number"], n), "ascii"))
     S = env.get_state()
     line = {
         "metric": "rendered env-steps/s @4096 envs 64x64 RGB; served p50/p99 step latency vs plain",
@@ -481,6 +490,7 @@ def main() -> int:
                      "frac_of_write_ceiling": achieved / write_ceiling},
         "single_slot": single,
         "distance_shading": shaded,
+        "ascii_maps": ascii_maps,
         "obs_write_gbs": ab["obs"] * n * K / sec / 1e9,
         "episodes_completed": int(S["episode"].astype(np.int64).sum()),
         "wall_s": wall,

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define JX_ABI_VERSION 2
+#define JX_ABI_VERSION 3
 
 typedef int32_t jx_status;
 #define JX_OK 0
@@ -75,6 +75,22 @@ typedef struct {
    * Sprites, ceiling and floor are not shaded.  0 = off. */
   int32_t shade_levels;
   float shade_dist;
+  /* Layout source: NULL = a seeded maze (the env seed; loop_frac applies).
+   * Otherwise a NUL-terminated ASCII map with the paper's Table 2 symbols, rows
+   * separated by '\n', placed at the top-left of the side x side grid (tiles it
+   * does not cover are walls): '#' wall (colour palette[id mod K]), '1'..'9'
+   * coloured walls, '.' or ' ' floor, 'S' spawn candidate, 'G' goal candidate,
+   * 'r' 'b' 'y' red, blue, yellow key (at most one per colour), '"' and '\'
+   * blue and yellow unlocked doors, 'R' 'B' 'Y' red, blue and yellow locked
+   * doors (at most 16 doors).  Border tiles must be walls.  Rules (the
+   * library's reading): each episode draws the spawn among the 'S' tiles (every
+   * floor tile if none) and the goal among the 'G' tiles (the tile farthest from
+   * the spawn, doors passable, if none); an unlocked door opens when the agent
+   * walks into it (that move is refused); picking up a key (reward r_key) opens
+   * every locked door of its colour; keys are drawn as billboards.  key_door
+   * and max_decor must be 0.  The text is read by the call that takes the
+   * configuration and need not outlive it. */
+  const char* ascii_map;
 } jx_env_cfg;
 
 typedef struct jx_ctx jx_ctx;

@@ -34,6 +34,7 @@ struct jx_ctx {
   Layout L{};
   DevState S{};
   std::vector<jx_env_cfg> cfgs;
+  std::vector<std::string> ascii_texts;  // copies of the configurations' ASCII maps
   std::vector<int32_t> cfg_idx;
   std::vector<int64_t> obs_off;
   std::vector<DevCfg> dev_cfgs;
@@ -77,6 +78,13 @@ bool validate_cfg(const jx_env_cfg& c, std::string* why) {
   if (c.shade_levels < 0 || c.shade_levels > kMaxShadeLevels) return bad("shade_levels must be in 0..16");
   if (c.shade_levels > 0 && !(c.shade_dist > 0.f && std::isfinite(c.shade_dist)))
     return bad("shade_dist must be finite and > 0 when shading is on");
+  if (c.ascii_map) {
+    if (c.key_door || c.max_decor) return bad("an ascii map brings its own keys and doors: key_door and max_decor must be 0");
+    std::vector<uint8_t> g((size_t)c.side * c.side);
+    int32_t keys[3];
+    std::string w;
+    if (parse_ascii_map(c.ascii_map, c.side, g.data(), keys, &w) < 0) return bad(w.c_str());
+  }
   return true;
 }
 
@@ -102,6 +110,7 @@ DevCfg derive_cfg(const jx_env_cfg& c) {
   d.shade_levels = c.shade_levels;
   d.shade_scale = c.shade_levels > 0 ? (float)((double)c.shade_levels / (double)c.shade_dist) : 0.f;
   d.shade_mul = c.shade_levels > 0 ? (65536u + (uint32_t)c.shade_levels - 1u) / (uint32_t)c.shade_levels : 0u;
+  d.ascii = c.ascii_map ? 1 : 0;
   return d;
 }
 
@@ -126,6 +135,8 @@ Layout make_layout(int n, int n_cfgs, int64_t maps_bytes) {
   L.door = take(4 * nn);
   L.key = take(4 * nn);
   L.decor = take(8 * nn);
+  L.akey = take(12 * nn);
+  L.doors = take(4 * nn);
   L.flags = take(nn);
   L.events = take(nn);
   L.ndecor = take(nn);
@@ -150,6 +161,9 @@ int64_t map_bytes_of(int side) { return align_up((int64_t)side * side, 16); }
 // kernels then read the configuration from the kernel argument and compute map
 // and frame offsets from the env index.
 void set_uniform(DevState* s, const jx_env_cfg* cfgs, int n_cfgs, const std::vector<int32_t>& idx) {
+  s->any_ascii = 0;
+  for (int k = 0; k < n_cfgs; ++k)
+    if (cfgs[k].ascii_map) s->any_ascii = 1;
   bool one = n_cfgs >= 1;
   for (size_t i = 1; i < idx.size() && one; ++i) one = idx[i] == idx[0];
   s->uniform = 0;
@@ -172,6 +186,8 @@ DevState bind_state(uint8_t* ws, const Layout& L, int n) {
   s.door = (int32_t*)(ws + L.door);
   s.key = (int32_t*)(ws + L.key);
   s.decor = (int32_t*)(ws + L.decor);
+  s.akey = (int32_t*)(ws + L.akey);
+  s.doors = (uint32_t*)(ws + L.doors);
   s.flags = ws + L.flags;
   s.events = ws + L.events;
   s.ndecor = ws + L.ndecor;
@@ -226,6 +242,7 @@ jx_status build_image(int n, const uint64_t* seeds, const jx_env_cfg* cfgs, int 
   std::memcpy(b + L.map_off, moff.data(), 4 * (size_t)n);
   std::memcpy(b + L.obs_off, obs_off->data(), 8 * (size_t)(n + 1));
   for (int i = 0; i < n; ++i) ((int32_t*)(b + L.decor))[2 * i] = ((int32_t*)(b + L.decor))[2 * i + 1] = -1;
+  for (int i = 0; i < 3 * n; ++i) ((int32_t*)(b + L.akey))[i] = -1;
   // costliest envs first for the persistent queue (frame bytes, then map side)
   std::vector<int32_t> order(n);
   std::iota(order.begin(), order.end(), 0);
@@ -247,7 +264,13 @@ jx_status build_image(int n, const uint64_t* seeds, const jx_env_cfg* cfgs, int 
     thr.emplace_back([&, tI] {
       for (int i = tI; i < n; i += n_thr) {
         const jx_env_cfg& c = cfgs[idx[i]];
-        if (!make_maze(seeds[i], c.side, c.loop_frac, b + L.maps + moff[i])) okv[tI] = 0;
+        if (c.ascii_map) {
+          int32_t keys[3];
+          if (parse_ascii_map(c.ascii_map, c.side, b + L.maps + moff[i], keys, nullptr) < 0) okv[tI] = 0;
+          std::memcpy(b + L.akey + 12 * (int64_t)i, keys, 12);
+        } else if (!make_maze(seeds[i], c.side, c.loop_frac, b + L.maps + moff[i])) {
+          okv[tI] = 0;
+        }
       }
     });
   }
@@ -367,6 +390,14 @@ jx_status jx_reset(jx_ctx* c, int32_t n_envs, const uint64_t* seeds, const jx_en
   c->n = n_envs;
   c->S = bind_state(c->ws, L, n_envs);
   c->cfgs.assign(cfgs, cfgs + n_cfgs);
+  // the caller's map texts need not outlive this call: keep copies
+  c->ascii_texts.assign(n_cfgs, std::string());
+  for (int k = 0; k < n_cfgs; ++k) {
+    if (cfgs[k].ascii_map) {
+      c->ascii_texts[k] = cfgs[k].ascii_map;
+      c->cfgs[k].ascii_map = c->ascii_texts[k].c_str();
+    }
+  }
   c->cfg_idx = idx;
   c->obs_off = oo;
   c->dev_cfgs.clear();
@@ -537,6 +568,8 @@ jx_status jx_state_layout(const jx_ctx* c, jx_field* f, int32_t cap, int32_t* n_
              {"door", L.door, 4, n},
              {"key", L.key, 4, n},
              {"decor", L.decor, 4, 2 * (int64_t)n},
+             {"akey", L.akey, 4, 3 * (int64_t)n},
+             {"doors", L.doors, 4, n},
              {"flags", L.flags, 1, n},
              {"events", L.events, 1, n},
              {"n_decor", L.ndecor, 1, n},
@@ -611,14 +644,20 @@ jx_status jx_set_state(jx_ctx* c, const void* host, size_t bytes) {
     uint32_t moff;
     std::memcpy(&moff, b + L.map_off + 4 * i, 4);
     bool ok = std::isfinite(x) && std::isfinite(y) && std::isfinite(th) && x >= 0.f && y >= 0.f &&
-              x < (float)N && y < (float)N && nd <= kMaxDecor && b[L.flags + i] <= 3 &&
+              x < (float)N && y < (float)N && nd <= kMaxDecor && b[L.flags + i] <= 31 &&
               moff + (uint64_t)NN <= (uint64_t)(L.rdesc - L.maps);
     for (int k = 0; k < 5; ++k) ok = ok && ids[k] >= -1 && ids[k] < NN;
+    for (int k = 0; k < 3; ++k) {
+      int32_t ak;
+      std::memcpy(&ak, b + L.akey + 12 * (int64_t)i + 4 * k, 4);
+      ok = ok && ak >= -1 && ak < NN;
+    }
     if (ok) {
-      // every border tile of the map must block (the walks rely on it)
+      // every border tile of the map must be a wall (the walks rely on it)
       const uint8_t* m = b + L.maps + moff;
+      auto wall = [](uint8_t v) { return !(v & kTileDoor) && (v & 0x0F) != 0; };
       for (int k = 0; k < N && ok; ++k)
-        ok = m[k] && m[(N - 1) * N + k] && m[k * N] && m[k * N + N - 1];
+        ok = wall(m[k]) && wall(m[(N - 1) * N + k]) && wall(m[k * N]) && wall(m[k * N + N - 1]);
     }
     for (int k = 0; k < nd; ++k) ok = ok && ids[3 + k] >= 0;
     if (!ok) return set_error(JX_EINVAL, "state image: env " + std::to_string(i) + " holds an out-of-range value");
@@ -668,6 +707,11 @@ jx_status jx_make_layout(uint64_t seed, const jx_env_cfg* cfg, uint8_t* grid) {
   if (!cfg || !grid) return set_error(JX_EINVAL, "null argument");
   std::string why;
   if (!validate_cfg(*cfg, &why)) return set_error(JX_EINVAL, why);
+  if (cfg->ascii_map) {
+    int32_t keys[3];
+    if (parse_ascii_map(cfg->ascii_map, cfg->side, grid, keys, &why) < 0) return set_error(JX_EINVAL, why);
+    return JX_OK;
+  }
   if (!make_maze(seed, cfg->side, cfg->loop_frac, grid)) return set_error(JX_EINVAL, "maze generation failed");
   return JX_OK;
 }

@@ -15,9 +15,11 @@ constexpr uint32_t kStateMagic = 0x4A585331u;  // "JXS1"
 
 // Event bits written per env and step.
 constexpr uint32_t EV_BLOCKED_X = 0x01, EV_BLOCKED_Y = 0x02, EV_KEY = 0x04, EV_GOAL = 0x08,
-                   EV_TRUNC = 0x10, EV_INVALID = 0x20, EV_RESET = 0x40;
+                   EV_TRUNC = 0x10, EV_INVALID = 0x20, EV_RESET = 0x40, EV_DOOR = 0x80;
 // Per-env flag bits.
 constexpr uint32_t FL_KEY = 0x01, FL_DOOR_OPEN = 0x02;
+// ASCII maps: key c (0 red, 1 blue, 2 yellow) taken
+constexpr uint32_t FL_AKEY0 = 0x04;
 
 enum Mode : int32_t { MODE_STEP = 0, MODE_RESET = 1, MODE_RENDER = 2 };
 
@@ -30,8 +32,10 @@ struct DevCfg {
   uint32_t shade_mul;  // ceil(2^16 / shade_levels): x / S == (x * shade_mul) >> 16 for x < 4096
   float move, turn, pr2, r_goal;
   float r_key, tanH, inv_tanH, inv_w;  // 1/tanH and 1/obs_w, rounded to float
+  int32_t ascii;  // 1: the layout is an ASCII map (doors, keys, candidates)
+  int32_t pad3[3];
 };
-static_assert(sizeof(DevCfg) == 80, "DevCfg layout");
+static_assert(sizeof(DevCfg) == 96, "DevCfg layout");
 
 // First 256 bytes of every workspace.
 struct WsHeader {
@@ -69,6 +73,8 @@ struct DevState {
   int32_t* door;
   int32_t* key;
   int32_t* decor;     // [n][2]
+  int32_t* akey;      // [n][3] ASCII maps: red, blue, yellow key tiles (-1 absent)
+  uint32_t* doors;    // ASCII maps: doors open (bit = door index)
   uint8_t* flags;
   uint8_t* events;
   uint8_t* ndecor;
@@ -87,6 +93,7 @@ struct DevState {
   // One configuration for every env: the kernels take it from here and derive
   // map and frame offsets from the env index (no dependent loads).
   int32_t uniform;
+  int32_t any_ascii;  // some configuration is an ASCII map (host-set; picks the kernel variant)
   DevCfg ucfg;
   int64_t map_stride;
   int64_t obs_stride;
@@ -113,7 +120,7 @@ struct ServeItem {
 
 // Workspace layout: byte offsets of every array.
 struct Layout {
-  int64_t hdr, x, y, th, t, ep, goal, door, key, decor, flags, events, ndecor, invalid, seed,
+  int64_t hdr, x, y, th, t, ep, goal, door, key, decor, akey, doors, flags, events, ndecor, invalid, seed,
       cfg_idx, map_off, obs_off, order, rdesc, queues, cfgs, maps, total;
 };
 

@@ -34,9 +34,23 @@ constexpr uint32_t rgb(uint32_t r, uint32_t g, uint32_t b) { return r | (g << 8)
 // wait for every frame store the wave has in flight.
 constexpr int kColorWords = 32;
 constexpr int kClrPalette = 0;  // 8 wall colours, indexed by tile id mod K
+constexpr int kClrWall9 = 8;    // ASCII maps: walls '1'..'9'
+constexpr int kClrDoor = 17;    // ASCII maps: doors by type (8 slots; 5 types)
 constexpr uint32_t kColorTable[kColorWords] = {
     rgb(180, 40, 40), rgb(40, 160, 40),  rgb(40, 60, 180),  rgb(190, 170, 40),
-    rgb(150, 40, 170), rgb(40, 160, 170), rgb(200, 110, 30), rgb(150, 150, 150)};
+    rgb(150, 40, 170), rgb(40, 160, 170), rgb(200, 110, 30), rgb(150, 150, 150),
+    rgb(180, 40, 40), rgb(40, 160, 40),  rgb(40, 60, 180),  rgb(190, 170, 40),
+    rgb(150, 40, 170), rgb(40, 160, 170), rgb(200, 110, 30), rgb(150, 150, 150),
+    rgb(230, 230, 230),
+    rgb(120, 0, 0), rgb(0, 30, 130), rgb(140, 120, 0), rgb(70, 110, 230), rgb(230, 200, 60),
+    rgb(120, 0, 0), rgb(120, 0, 0), rgb(120, 0, 0)};
+// ASCII maps: key billboards by colour (red, blue, yellow)
+constexpr uint32_t kAKeyRgb[3] = {rgb(255, 40, 40), rgb(40, 110, 255), rgb(255, 200, 40)};
+// Tile bytes (layout sources): low nibble wall class (1 default, 2..10 '1'..'9'),
+// bit 7 door (type in bits 4..6, index in 0..3), bits 5/6 spawn/goal candidates
+// on floor tiles.
+constexpr uint32_t kTileDoor = 0x80u, kTileSpawn = 0x20u, kTileGoal = 0x40u;
+constexpr uint32_t kDoorBlueUnlocked = 3u, kDoorYellowUnlocked = 4u;
 
 __device__ __forceinline__ void stage_colors(uint32_t* lclr) {
   if (threadIdx.x == 0) {
@@ -164,18 +178,48 @@ struct Episode {
 };
 
 // Episode reset for episode `e` of the env with layout in `lmap` (0 floor).
+// ASC: the batch may hold ASCII maps (else that code is compiled out).
+template <bool ASC>
 __device__ Episode episode_reset(const DevCfg& cf, const uint8_t* lmap, uint64_t seed, uint32_t e,
                                  int lane) {
   const int N = cf.side;
   uint64_t s = seed ^ sm_mix((uint64_t)e + 1ull);
-  uint64_t freem = 0ull;
+  // lane y: row y as bit masks of floor tiles, spawn and goal candidates, doors
+  uint64_t freem = 0ull, spawnm = 0ull, goalm = 0ull, doorm = 0ull;
   if (lane < N) {
     const uint8_t* row = lmap + lane * N;
-    for (int xx = 0; xx < N; ++xx)
-      if (row[xx] == 0) freem |= 1ull << xx;
+    for (int xx = 0; xx < N; ++xx) {
+      const uint32_t v = row[xx];
+      const uint64_t bit = 1ull << xx;
+      if ((v & 0x8Fu) == 0u) {
+        freem |= bit;
+        if (v & kTileSpawn) spawnm |= bit;
+        if (v & kTileGoal) goalm |= bit;
+      }
+      if (v & kTileDoor) doorm |= bit;
+    }
   }
   const uint32_t n_free = mask_count(freem, lane);
   Episode ep;
+  if (ASC && cf.ascii) {
+    // ASCII maps: spawn among the spawn candidates (every floor tile if none),
+    // heading, goal among the goal candidates (else the farthest tile from the
+    // spawn with doors passable, smallest id); keys and doors come from the map
+    const uint32_t n_s = mask_count(spawnm, lane);
+    const int spawn = n_s ? mask_select(spawnm, sm_draw(s, n_s), N, lane)
+                          : mask_select(freem, sm_draw(s, n_free), N, lane);
+    const uint32_t k24 = (uint32_t)(sm_next(s) >> 40);
+    ep.th = (float)k24 * (kTwoPiF * 0x1p-24f);
+    ep.x = (float)(spawn % N) + 0.5f;
+    ep.y = (float)(spawn / N) + 0.5f;
+    const uint32_t n_g = mask_count(goalm, lane);
+    ep.goal = n_g ? mask_select(goalm, sm_draw(s, n_g), N, lane)
+                  : mask_first(bfs_rows(freem | doorm, spawn, N, -1, lane).frontier, N);
+    ep.door = ep.key = -1;
+    ep.nd = 0;
+    ep.dec0 = ep.dec1 = -1;
+    return ep;
+  }
   const int spawn = mask_select(freem, sm_draw(s, n_free), N, lane);
   const uint32_t k24 = (uint32_t)(sm_next(s) >> 40);
   ep.th = (float)k24 * (kTwoPiF * 0x1p-24f);
@@ -328,21 +372,29 @@ struct ColDbg {
 // Casts the env's columns and reduces each to a span record in lcol (and
 // writes debug records when asked).
 // sn, cs: sine and cosine of the heading.
+template <bool ASC>
 __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int lane, uint8_t* lmap,
                                const uint32_t* lclr,
                                uint32_t* lcol, float x, float y, float sn, float cs, int goal,
-                               int door, int key, uint32_t fl, int nd, int dec0, int dec1) {
+                               int door, int key, uint32_t fl, int nd, int dec0, int dec1,
+                               uint32_t doors, int ak0, int ak1, int ak2) {
   const int N = cf.side, H = cf.obs_h, W = cf.obs_w, K = cf.n_colors, S_lv = cf.shade_levels;
   // the shut locked door blocks rays like a wall (tile id `shut`, -1 if none)
   const int shut = (door >= 0 && !(fl & FL_DOOR_OPEN)) ? door : -1;
   const float tanH = cf.tanH;
   const float px = -sn * tanH, py = cs * tanH;
 
-  // Sprites in fixed slots, in painting-index order: key, goal, decor 0, decor 1.
-  // Empty slots are skipped, which keeps the relative order of the active ones.
-  const int sid[4] = {(key >= 0 && !(fl & FL_KEY)) ? key : -1, (cf.goal_sprite && goal >= 0) ? goal : -1,
-                      nd > 0 ? dec0 : -1, nd > 1 ? dec1 : -1};
-  const uint32_t srgb[4] = {kKeyRgb, kGoalRgb, kDecorRgb, kDecorRgb};
+  // Sprites in fixed slots, in painting-index order: key, goal, decor 0, decor 1
+  // (ASCII maps: red, blue, yellow key, goal).  Empty slots are skipped, which
+  // keeps the relative order of the active ones.
+  const bool asc = ASC && cf.ascii != 0;
+  const int gsp = (cf.goal_sprite && goal >= 0) ? goal : -1;
+  const int sid[4] = {asc ? ((ak0 >= 0 && !(fl & FL_AKEY0)) ? ak0 : -1) : ((key >= 0 && !(fl & FL_KEY)) ? key : -1),
+                      asc ? ((ak1 >= 0 && !(fl & (FL_AKEY0 << 1))) ? ak1 : -1) : gsp,
+                      asc ? ((ak2 >= 0 && !(fl & (FL_AKEY0 << 2))) ? ak2 : -1) : (nd > 0 ? dec0 : -1),
+                      asc ? gsp : (nd > 1 ? dec1 : -1)};
+  const uint32_t srgb[4] = {asc ? kAKeyRgb[0] : kKeyRgb, asc ? kAKeyRgb[1] : kGoalRgb,
+                            asc ? kAKeyRgb[2] : kDecorRgb, asc ? kGoalRgb : kDecorRgb};
   float sY[4], sU[4], sHW[4], sHS[4];
   bool sVis[4];
   const float halfW = 0.5f * (float)W;
@@ -383,6 +435,7 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
     const float dtx = rx != 0.f ? fabsf(ivx) : 0.f, dty = ry != 0.f ? fabsf(ivy) : 0.f;
     float tst = INF;
     int side = 0, hit = -1, cell = 1;
+    uint32_t hv = 1u;  // tile byte of the hit
     // Branch-free walk in batches: the sequence of tiles a ray crosses does
     // not depend on the map, only where it stops does.  Each batch computes
     // the next kDdaBatch crossings (one grid line each: the tile index moves
@@ -413,30 +466,51 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
       }
       // bit u: crossing u stops the walk (blocking tile, shut door, or off the map)
       uint32_t stop = 0;
+      uint32_t vs[kDdaBatch];
 #pragma unroll
       for (int u = 0; u < kDdaBatch; ++u) {
         const uint32_t uid = (uint32_t)ids[u];
-        const uint32_t v = lmap[uid < last ? uid : last];
-        stop |= (uint32_t)((v != 0u) | (ids[u] == shut) | (uid > last)) << u;
+        vs[u] = lmap[uid < last ? uid : last];
+      }
+      if (asc) {
+        // map doors block while their bit in `doors` is clear
+#pragma unroll
+        for (int u = 0; u < kDdaBatch; ++u) {
+          const uint32_t v = vs[u];
+          const bool open = (v & kTileDoor) && ((doors >> (v & 15u)) & 1u);
+          stop |= (uint32_t)((((v & 0x8Fu) != 0u) && !open) | ((uint32_t)ids[u] > last)) << u;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kDdaBatch; ++u)
+          stop |= (uint32_t)((vs[u] != 0u) | (ids[u] == shut) | ((uint32_t)ids[u] > last)) << u;
       }
       tst = ts[kDdaBatch - 1];  // kept only if nothing in the batch stops the walk
       side = sd[kDdaBatch - 1] ? 1 : 0;
       if (stop) {
         int sid_ = ids[kDdaBatch - 1];
+        uint32_t sv = vs[kDdaBatch - 1];
 #pragma unroll
         for (int u = kDdaBatch - 2; u >= 0; --u) {  // the earliest stop wins
           const bool b = (stop >> u) & 1u;
           tst = b ? ts[u] : tst;
           side = b ? (sd[u] ? 1 : 0) : side;
           sid_ = b ? ids[u] : sid_;
+          sv = b ? vs[u] : sv;
         }
         found = true;
         const bool out = (uint32_t)sid_ > last;
         hit = out ? -1 : sid_;
-        cell = (!out && sid_ == shut) ? 2 : 1;
+        hv = out ? 1u : sv;
+        cell = (!out && (sid_ == shut || (hv & kTileDoor))) ? 2 : 1;
       }
     }
-    uint32_t wc = (cell == 2) ? kDoor : lclr[kClrPalette + (hit < 0 ? 0 : hit) % K];
+    uint32_t wc;
+    const uint32_t wcls = hv & 15u;
+    if (asc && (hv & kTileDoor)) wc = lclr[kClrDoor + ((hv >> 4) & 7u)];
+    else if (cell == 2) wc = kDoor;
+    else if (asc && wcls >= 2u && wcls <= 10u) wc = lclr[kClrWall9 + wcls - 2u];
+    else wc = lclr[kClrPalette + (hit < 0 ? 0 : hit) % K];
     if (side) wc = (wc >> 1) & 0x7F7F7Fu;
     if (S_lv > 0) {
       // distance shading: level l = min(floor(t* S / D), S - 1), each channel
@@ -526,7 +600,7 @@ struct EnvOut {
   int64_t obs_off;
   int env, W, H, mode;
   float x, y, th, reward;
-  uint32_t t, ep, fl, nd, ev, done;
+  uint32_t t, ep, fl, nd, ev, done, doors;
   int goal, door, key, dec0, dec1;
 };
 
@@ -538,8 +612,9 @@ struct EnvIn {
   DevCfg cf;
   int env;
   float x, y, th;
-  uint32_t t, ep, fl;
+  uint32_t t, ep, fl, doors;
   int goal, door, key, dec0, dec1, nd;
+  int ak0, ak1, ak2;  // ASCII maps: key tiles (constant per env)
   uint64_t seed;
   uint32_t map[kMapWords];
 };
@@ -569,6 +644,23 @@ __device__ __forceinline__ void load_env(const DevState& S, int env, int lane, E
   in.fl = S.flags[env];
   in.nd = S.ndecor[env];
   in.seed = S.seed[env];
+  in.doors = S.doors[env];
+  in.ak0 = S.akey[3 * env];
+  in.ak1 = S.akey[3 * env + 1];
+  in.ak2 = S.akey[3 * env + 2];
+}
+
+// Bit mask of the map's locked doors of colour c (door type c), gathered by
+// the whole wave from its LDS map.
+__device__ uint32_t locked_doors_of(const uint8_t* lmap, int NN, uint32_t c, int lane) {
+  uint32_t m = 0u;
+  for (int i = lane; i < NN; i += 64) {
+    const uint32_t v = lmap[i];
+    if ((v & kTileDoor) && ((v >> 4) & 7u) == c) m |= 1u << (v & 15u);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m |= (uint32_t)__shfl_xor((int)m, off, 64);
+  return m;
 }
 
 // Copies the env's layout words from registers into the wave's LDS map.  The
@@ -590,7 +682,7 @@ __device__ __forceinline__ void stage_map(const EnvIn<MAXN>& in, int lane, uint8
 // outstanding stores).  All lanes run the uniform parts redundantly.
 // STAGE: copy the layout into LDS first (else it is already there).
 // action < 0: read this env's action from io.act.
-template <int MAXN, bool STAGE = true>
+template <int MAXN, bool STAGE, bool ASC>
 __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevIo& io, int action,
                             int lane, uint8_t* lmap, const uint32_t* lclr, uint32_t* lcol, EnvOut& o) {
   const DevCfg& cf = in.cf;
@@ -602,6 +694,7 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   int goal = in.goal, door = in.door, key = in.key;
   int dec0 = in.dec0, dec1 = in.dec1;
   uint32_t fl = in.fl;
+  uint32_t doors = in.doors;
   int nd = in.nd;
   const uint64_t seed = in.seed;
   wave_sync();
@@ -643,17 +736,40 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
     auto blocks = [&](int tx, int ty) -> bool {
       if ((unsigned)tx >= (unsigned)N || (unsigned)ty >= (unsigned)N) return true;
       const int id = ty * N + tx;
-      return lmap[id] != 0 || (dclosed && id == door);
+      const uint32_t v = lmap[id];
+      if (ASC && (v & kTileDoor)) return !((doors >> (v & 15u)) & 1u);  // map door: shut unless open
+      return (v & 0x0Fu) != 0u || (dclosed && id == door);
+    };
+    // ASCII maps: walking into a shut unlocked door opens it (the move is refused)
+    auto bump = [&](int tx, int ty) {
+      if ((unsigned)tx >= (unsigned)N || (unsigned)ty >= (unsigned)N) return;
+      const uint32_t v = lmap[ty * N + tx];
+      const uint32_t type = (v >> 4) & 7u;
+      if ((v & kTileDoor) && (type == kDoorBlueUnlocked || type == kDoorYellowUnlocked) &&
+          !((doors >> (v & 15u)) & 1u)) {
+        doors |= 1u << (v & 15u);
+        ev |= EV_DOOR;
+      }
     };
     if (mx != 0.f) {
       const float nx = x + mx;
-      if (!blocks((int)floorf(nx), (int)floorf(y))) x = nx;
-      else ev |= EV_BLOCKED_X;
+      const int tx = (int)floorf(nx), ty = (int)floorf(y);
+      if (!blocks(tx, ty)) {
+        x = nx;
+      } else {
+        ev |= EV_BLOCKED_X;
+        if (ASC) bump(tx, ty);
+      }
     }
     if (my != 0.f) {
       const float ny = y + my;
-      if (!blocks((int)floorf(x), (int)floorf(ny))) y = ny;
-      else ev |= EV_BLOCKED_Y;
+      const int tx = (int)floorf(x), ty = (int)floorf(ny);
+      if (!blocks(tx, ty)) {
+        y = ny;
+      } else {
+        ev |= EV_BLOCKED_Y;
+        if (ASC) bump(tx, ty);
+      }
     }
     if (key >= 0 && !(fl & FL_KEY)) {
       const float dx = x - ((float)(key % N) + 0.5f);
@@ -662,6 +778,24 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
         fl |= FL_KEY | FL_DOOR_OPEN;
         reward += cf.r_key;
         ev |= EV_KEY;
+      }
+    }
+    if (ASC && cf.ascii) {
+      // ASCII maps: picking up the key of colour c opens every locked door of colour c
+      const int ak[3] = {in.ak0, in.ak1, in.ak2};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (ak[c] < 0 || (fl & (FL_AKEY0 << c))) continue;
+        const float dx = x - ((float)(ak[c] % N) + 0.5f);
+        const float dy = y - ((float)(ak[c] / N) + 0.5f);
+        if (dx * dx + dy * dy < cf.pr2) {
+          fl |= FL_AKEY0 << c;
+          reward += cf.r_key;
+          ev |= EV_KEY;
+          const uint32_t m = locked_doors_of(lmap, N * N, (uint32_t)c, lane);
+          if (m & ~doors) ev |= EV_DOOR;
+          doors |= m;
+        }
       }
     }
     bool term = false;
@@ -677,7 +811,7 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   }
   if (mode == MODE_RESET || done) {
     const uint32_t e = (mode == MODE_RESET) ? 0u : ep + 1u;
-    const Episode n = episode_reset(cf, lmap, seed, e, lane);
+    const Episode n = episode_reset<ASC>(cf, lmap, seed, e, lane);
     x = n.x;
     y = n.y;
     th = n.th;
@@ -690,12 +824,14 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
     t = 0;
     ep = e;
     fl = 0;
+    doors = 0u;
     if (done) ev |= EV_RESET;
     heading_changed = true;
   }
   if (heading_changed) sincosf(th, &sn, &cs);
   if (io.obs || io.dbg)
-    render_columns(cf, io, env, lane, lmap, lclr, lcol, x, y, sn, cs, goal, door, key, fl, nd, dec0, dec1);
+    render_columns<ASC>(cf, io, env, lane, lmap, lclr, lcol, x, y, sn, cs, goal, door, key, fl, nd, dec0, dec1,
+                   doors, in.ak0, in.ak1, in.ak2);
   o.obs_off = 0;  // set by the caller (obs_off_of), outside any step loop
   o.env = env;
   o.W = cf.obs_w;
@@ -716,6 +852,7 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   o.key = key;
   o.dec0 = dec0;
   o.dec1 = dec1;
+  o.doors = doors;
 }
 
 // Scalar results of one env-step, stored by lane 0 with vector stores.
@@ -735,6 +872,7 @@ __device__ void write_back(const DevState& S, const DevIo& io, const EnvOut& o, 
   S.flags[env] = (uint8_t)o.fl;
   S.ndecor[env] = (uint8_t)o.nd;
   S.events[env] = (uint8_t)o.ev;
+  S.doors[env] = o.doors;
   if (o.ev & EV_INVALID) S.invalid[env] += 1u;
   if (o.mode == MODE_STEP) {
     io.rew[env] = o.reward;
@@ -748,13 +886,13 @@ __device__ __forceinline__ int64_t obs_off_of(const DevState& S, int env) {
 }
 
 // The whole per-env pipeline in one wave.
-template <int MAXN>
+template <int MAXN, bool ASC>
 __device__ __forceinline__ void process_env(const DevState& S, const DevIo& io, int env, int lane, uint8_t* lmap,
                             const uint32_t* lclr, uint32_t* lcol) {
   EnvIn<MAXN> in;
   load_env<MAXN>(S, env, lane, in);
   EnvOut o;
-  produce_env<MAXN>(in, S, io, -1, lane, lmap, lclr, lcol, o);
+  produce_env<MAXN, true, ASC>(in, S, io, -1, lane, lmap, lclr, lcol, o);
   o.obs_off = obs_off_of(S, env);
   if (io.obs) fill_frame(lcol, io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
   write_back(S, io, o, lane);
@@ -773,7 +911,7 @@ __device__ __forceinline__ DevIo io_of(const DevIo& io, const RolloutDesc* rd, i
   return r;
 }
 
-template <int MAXN, int WPB>
+template <int MAXN, int WPB, bool ASC>
 __global__ __launch_bounds__(64 * WPB) void k_plain(DevState S, DevIo io0, const RolloutDesc* rd,
                                                     int t) {
   __shared__ __align__(16) uint8_t smap[WPB][MAXN * MAXN];
@@ -784,7 +922,7 @@ __global__ __launch_bounds__(64 * WPB) void k_plain(DevState S, DevIo io0, const
   const int env = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + w);
   if (env >= S.n) return;
   const DevIo io = io_of(io0, rd, t);
-  process_env<MAXN>(S, io, env, lane, smap[w], sclr, scol[w]);
+  process_env<MAXN, ASC>(S, io, env, lane, smap[w], sclr, scol[w]);
 }
 
 // Work distribution of the persistent forms.  Items (positions in a work
@@ -843,7 +981,7 @@ __device__ __forceinline__ void queue_drain(const QueueView& v, int lane, F&& f)
   }
 }
 
-template <int WPB>
+template <int WPB, bool ASC>
 __global__ __launch_bounds__(64 * WPB) void k_persist(DevState S, DevIo io0, const RolloutDesc* rd,
                                                       int t, uint32_t seq) {
   __shared__ __align__(16) uint8_t smap[WPB][kMaxSide * kMaxSide];
@@ -855,7 +993,7 @@ __global__ __launch_bounds__(64 * WPB) void k_persist(DevState S, DevIo io0, con
   const QueueView v = queue_view<WPB>(S.queues, seq, S.n, w, lane);
   queue_drain(v, lane, [&](int pos) {
     const int env = __builtin_amdgcn_readfirstlane(S.order[pos]);
-    process_env<kMaxSide>(S, io, env, lane, smap[w], sclr, scol[w]);
+    process_env<kMaxSide, ASC>(S, io, env, lane, smap[w], sclr, scol[w]);
   });
 }
 
@@ -876,7 +1014,7 @@ __global__ __launch_bounds__(64 * WPB) void k_serve(const DevState* states, cons
     // fields are read from the descriptors where they are used (scalar loads)
     const DevState& S = states[d];
     const DevIo& io = ios[d];
-    process_env<kMaxSide>(S, io, env, lane, smap[w], sclr, scol[w]);
+    process_env<kMaxSide, true>(S, io, env, lane, smap[w], sclr, scol[w]);
   });
 }
 
@@ -888,7 +1026,7 @@ __global__ __launch_bounds__(64 * WPB) void k_serve(const DevState* states, cons
 // producing env k+1 overlaps writing env k, and the writer's outstanding stores
 // never stall a load.  Pairs walk the work order (costliest first) with a
 // static stride of all pairs in the grid.
-template <int MAXN, int P>
+template <int MAXN, int P, bool ASC>
 __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const RolloutDesc* rd,
                                                   int t) {
   __shared__ __align__(16) uint8_t smap[P][MAXN * MAXN];
@@ -914,7 +1052,7 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
         const int nitem = item + pairs;
         if (nitem < S.n) load_env<MAXN>(S, __builtin_amdgcn_readfirstlane(S.order[nitem]), lane, nxt);
         EnvOut o;
-        produce_env<MAXN>(cur, S, io, -1, lane, smap[pair], sclr, scol[pair][b], o);
+        produce_env<MAXN, true, ASC>(cur, S, io, -1, lane, smap[pair], sclr, scol[pair][b], o);
         o.obs_off = obs_off_of(S, o.env);
         if (lane == 0) sout[pair][b] = o;
         cur = nxt;
@@ -940,7 +1078,7 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
 // stores.  Waves take envs by a static stride over the work order.  Per step
 // the results are those of a single-step launch; the state is written back
 // once, after the last step.
-template <int MAXN, int WPB>
+template <int MAXN, int WPB, bool ASC>
 __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* act, uint8_t* obs,
                                                    int64_t obs_stride, float* rew, uint8_t* dn,
                                                    int T, int store_mode) {
@@ -984,7 +1122,7 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
         int ln = lane;
         asm volatile("" : "+v"(ln));
         EnvOut o;
-        produce_env<MAXN, false>(in, S, io, a, ln, smap[w], sclr, scol[w], o);
+        produce_env<MAXN, false, ASC>(in, S, io, a, ln, smap[w], sclr, scol[w], o);
         const int t = t0 + k;
         fill_frame(scol[w], obs + (int64_t)t * obs_stride + obs_off, o.W, o.H, ln, store_mode);
         if (lane == 0) {
@@ -1007,6 +1145,7 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
         in.key = (int)uniform_u((uint32_t)o.key);
         in.dec0 = (int)uniform_u((uint32_t)o.dec0);
         in.dec1 = (int)uniform_u((uint32_t)o.dec1);
+        in.doors = uniform_u(o.doors);
       }
     }
     if (lane == 0 && T > 0) {
@@ -1023,6 +1162,7 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
       S.flags[env] = (uint8_t)in.fl;
       S.ndecor[env] = (uint8_t)in.nd;
       S.events[env] = (uint8_t)last_ev;
+      S.doors[env] = in.doors;
       if (n_invalid) S.invalid[env] += n_invalid;
     }
   }
@@ -1036,15 +1176,15 @@ __global__ void k_set_desc(RolloutDesc* rd, RolloutDesc v) {
   if (threadIdx.x == 0) *rd = v;
 }
 
-template <int MAXN>
+template <int MAXN, bool ASC>
 int launch_plain_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb,
                    hipStream_t st) {
   const int grid = (s.n + wpb - 1) / wpb;
   switch (wpb) {
-    case 1: hipLaunchKernelGGL((k_plain<MAXN, 1>), dim3(grid), dim3(64), 0, st, s, io, rd, t); break;
-    case 2: hipLaunchKernelGGL((k_plain<MAXN, 2>), dim3(grid), dim3(128), 0, st, s, io, rd, t); break;
-    case 4: hipLaunchKernelGGL((k_plain<MAXN, 4>), dim3(grid), dim3(256), 0, st, s, io, rd, t); break;
-    case 8: hipLaunchKernelGGL((k_plain<MAXN, 8>), dim3(grid), dim3(512), 0, st, s, io, rd, t); break;
+    case 1: hipLaunchKernelGGL((k_plain<MAXN, 1, ASC>), dim3(grid), dim3(64), 0, st, s, io, rd, t); break;
+    case 2: hipLaunchKernelGGL((k_plain<MAXN, 2, ASC>), dim3(grid), dim3(128), 0, st, s, io, rd, t); break;
+    case 4: hipLaunchKernelGGL((k_plain<MAXN, 4, ASC>), dim3(grid), dim3(256), 0, st, s, io, rd, t); break;
+    case 8: hipLaunchKernelGGL((k_plain<MAXN, 8, ASC>), dim3(grid), dim3(512), 0, st, s, io, rd, t); break;
     default: return -1;
   }
   return (int)hipGetLastError();
@@ -1057,30 +1197,77 @@ inline bool mode_needs_plain(const DevIo& io, const RolloutDesc* rd) {
   return !rd && (io.mode != MODE_STEP || io.dbg != nullptr || io.obs == nullptr);
 }
 
-template <int MAXN>
+template <int MAXN, bool ASC>
 int launch_pipe_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int p, int groups,
                   hipStream_t st) {
   switch (p) {
-    case 1: hipLaunchKernelGGL((k_pipe<MAXN, 1>), dim3(groups), dim3(128), 0, st, s, io, rd, t); break;
-    case 2: hipLaunchKernelGGL((k_pipe<MAXN, 2>), dim3(groups), dim3(256), 0, st, s, io, rd, t); break;
-    case 4: hipLaunchKernelGGL((k_pipe<MAXN, 4>), dim3(groups), dim3(512), 0, st, s, io, rd, t); break;
+    case 1: hipLaunchKernelGGL((k_pipe<MAXN, 1, ASC>), dim3(groups), dim3(128), 0, st, s, io, rd, t); break;
+    case 2: hipLaunchKernelGGL((k_pipe<MAXN, 2, ASC>), dim3(groups), dim3(256), 0, st, s, io, rd, t); break;
+    case 4: hipLaunchKernelGGL((k_pipe<MAXN, 4, ASC>), dim3(groups), dim3(512), 0, st, s, io, rd, t); break;
     default: return -1;
   }
   return (int)hipGetLastError();
 }
 
-template <int MAXN>
+template <int MAXN, bool ASC>
 int launch_roll_n(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride, float* rew,
                   uint8_t* dn, int T, int wpb, int groups, int nt, hipStream_t st) {
   switch (wpb) {
-    case 1: hipLaunchKernelGGL((k_roll<MAXN, 1>), dim3(groups), dim3(64), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
-    case 2: hipLaunchKernelGGL((k_roll<MAXN, 2>), dim3(groups), dim3(128), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
-    case 4: hipLaunchKernelGGL((k_roll<MAXN, 4>), dim3(groups), dim3(256), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
-    case 8: hipLaunchKernelGGL((k_roll<MAXN, 8>), dim3(groups), dim3(512), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
+    case 1: hipLaunchKernelGGL((k_roll<MAXN, 1, ASC>), dim3(groups), dim3(64), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
+    case 2: hipLaunchKernelGGL((k_roll<MAXN, 2, ASC>), dim3(groups), dim3(128), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
+    case 4: hipLaunchKernelGGL((k_roll<MAXN, 4, ASC>), dim3(groups), dim3(256), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
+    case 8: hipLaunchKernelGGL((k_roll<MAXN, 8, ASC>), dim3(groups), dim3(512), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
     default: return -1;
   }
   return (int)hipGetLastError();
 }
+
+template <bool ASC>
+int launch_persist_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb,
+                     int groups, uint32_t seq, hipStream_t st) {
+  switch (wpb) {
+    case 1: hipLaunchKernelGGL((k_persist<1, ASC>), dim3(groups), dim3(64), 0, st, s, io, rd, t, seq); break;
+    case 2: hipLaunchKernelGGL((k_persist<2, ASC>), dim3(groups), dim3(128), 0, st, s, io, rd, t, seq); break;
+    case 4: hipLaunchKernelGGL((k_persist<4, ASC>), dim3(groups), dim3(256), 0, st, s, io, rd, t, seq); break;
+    case 8: hipLaunchKernelGGL((k_persist<8, ASC>), dim3(groups), dim3(512), 0, st, s, io, rd, t, seq); break;
+    default: return -1;
+  }
+  return (int)hipGetLastError();
+}
+
+// Picks the kernel variant by the largest map side and by whether the batch
+// holds ASCII maps.
+template <template <int, bool> class L, typename... A>
+int by_shape(const DevState& s, int max_side, A&&... a) {
+  if (s.any_ascii) {
+    if (max_side <= 16) return L<16, true>::run(s, a...);
+    if (max_side <= 32) return L<32, true>::run(s, a...);
+    return L<64, true>::run(s, a...);
+  }
+  if (max_side <= 16) return L<16, false>::run(s, a...);
+  if (max_side <= 32) return L<32, false>::run(s, a...);
+  return L<64, false>::run(s, a...);
+}
+template <int MAXN, bool ASC>
+struct PlainL {
+  static int run(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb, hipStream_t st) {
+    return launch_plain_n<MAXN, ASC>(s, io, rd, t, wpb, st);
+  }
+};
+template <int MAXN, bool ASC>
+struct PipeL {
+  static int run(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int p, int groups,
+                 hipStream_t st) {
+    return launch_pipe_n<MAXN, ASC>(s, io, rd, t, p, groups, st);
+  }
+};
+template <int MAXN, bool ASC>
+struct RollL {
+  static int run(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride, float* rew,
+                 uint8_t* dn, int T, int wpb, int groups, int nt, hipStream_t st) {
+    return launch_roll_n<MAXN, ASC>(s, act, obs, obs_stride, rew, dn, T, wpb, groups, nt, st);
+  }
+};
 
 int launch_set_desc(RolloutDesc* rd_dev, const RolloutDesc& value, void* stream) {
   hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), rd_dev,
@@ -1099,11 +1286,7 @@ int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int 
   if (s.n <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int wpb = lc.waves_per_group;
-  if (lc.form == 0) {
-    if (max_side <= 16) return launch_plain_n<16>(s, io, rd, t, wpb, st);
-    if (max_side <= 32) return launch_plain_n<32>(s, io, rd, t, wpb, st);
-    return launch_plain_n<64>(s, io, rd, t, wpb, st);
-  }
+  if (lc.form == 0) return by_shape<PlainL>(s, max_side, io, rd, t, wpb, st);
   if (lc.form == 2) {
     // waves_per_group counts wave pairs (1, 2 or 4) in the pipelined form
     const int p = wpb > 4 ? 4 : wpb;
@@ -1111,23 +1294,15 @@ int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int 
     const int need = (s.n + p - 1) / p;
     if (groups > need) groups = need;
     if (groups < 1) groups = 1;
-    if (mode_needs_plain(io, rd)) return launch_plain_n<64>(s, io, rd, t, 1, st);
-    if (max_side <= 16) return launch_pipe_n<16>(s, io, rd, t, p, groups, st);
-    if (max_side <= 32) return launch_pipe_n<32>(s, io, rd, t, p, groups, st);
-    return launch_pipe_n<64>(s, io, rd, t, p, groups, st);
+    if (mode_needs_plain(io, rd)) return by_shape<PlainL>(s, 64, io, rd, t, 1, st);
+    return by_shape<PipeL>(s, max_side, io, rd, t, p, groups, st);
   }
   int groups = n_cu * lc.groups_per_cu;
   const int need = (s.n + wpb - 1) / wpb;
   if (groups > need) groups = need;
   if (groups < 1) groups = 1;
-  switch (wpb) {
-    case 1: hipLaunchKernelGGL((k_persist<1>), dim3(groups), dim3(64), 0, st, s, io, rd, t, seq); break;
-    case 2: hipLaunchKernelGGL((k_persist<2>), dim3(groups), dim3(128), 0, st, s, io, rd, t, seq); break;
-    case 4: hipLaunchKernelGGL((k_persist<4>), dim3(groups), dim3(256), 0, st, s, io, rd, t, seq); break;
-    case 8: hipLaunchKernelGGL((k_persist<8>), dim3(groups), dim3(512), 0, st, s, io, rd, t, seq); break;
-    default: return -1;
-  }
-  return (int)hipGetLastError();
+  return s.any_ascii ? launch_persist_n<true>(s, io, rd, t, wpb, groups, seq, st)
+                     : launch_persist_n<false>(s, io, rd, t, wpb, groups, seq, st);
 }
 
 int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeItem* items_dev,
@@ -1154,9 +1329,7 @@ int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, in
   int groups = (s.n + wpb - 1) / wpb;
   const int cap = n_cu * (16 / wpb > 0 ? 16 / wpb : 1);
   if (groups > cap) groups = cap;
-  if (max_side <= 16) return launch_roll_n<16>(s, act, obs, obs_stride, rew, dn, T, wpb, groups, lc.store_mode, st);
-  if (max_side <= 32) return launch_roll_n<32>(s, act, obs, obs_stride, rew, dn, T, wpb, groups, lc.store_mode, st);
-  return launch_roll_n<64>(s, act, obs, obs_stride, rew, dn, T, wpb, groups, lc.store_mode, st);
+  return by_shape<RollL>(s, max_side, act, obs, obs_stride, rew, dn, T, wpb, groups, lc.store_mode, st);
 }
 
 const char* kernel_error_string(int code) { return hipGetErrorString((hipError_t)code); }

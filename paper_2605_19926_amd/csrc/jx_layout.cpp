@@ -108,3 +108,70 @@ bool make_maze(uint64_t seed, int N, float loop_frac, uint8_t* grid) {
 }
 
 }  // namespace jx
+
+namespace jx {
+
+int parse_ascii_map(const char* text, int N, uint8_t* grid, int32_t keys[3], std::string* why) {
+  auto fail = [&](const char* m) {
+    if (why) *why = m;
+    return -1;
+  };
+  if (!text || !grid || N < 5 || N > 64) return fail("bad arguments");
+  for (int i = 0; i < N * N; ++i) grid[i] = 1;
+  keys[0] = keys[1] = keys[2] = -1;
+  int col = 0, row = 0, n_doors = 0, n_floor = 0;
+  for (const char* p = text; *p != '\0'; ++p) {
+    const char ch = *p;
+    if (ch == '\r') continue;
+    if (ch == '\n') {
+      ++row;
+      col = 0;
+      continue;
+    }
+    if (row >= N || col >= N) return fail("ascii map larger than side x side");
+    uint8_t tile = 0;
+    switch (ch) {
+      case '#': tile = 1; break;
+      case '.':
+      case ' ': tile = 0; break;
+      case 'S': tile = kTileSpawn; break;
+      case 'G': tile = kTileGoal; break;
+      case 'r':
+      case 'b':
+      case 'y': {
+        const int k = (ch == 'r') ? 0 : (ch == 'b') ? 1 : 2;
+        if (keys[k] >= 0) return fail("ascii map has two keys of one colour");
+        keys[k] = row * N + col;
+        break;
+      }
+      case 'R':
+      case 'B':
+      case 'Y':
+      case '"':
+      case '\\': {
+        if (n_doors == kMaxDoors) return fail("ascii map has more than 16 doors");
+        const int type = (ch == 'R') ? kDoorRedLocked : (ch == 'B') ? kDoorBlueLocked
+                         : (ch == 'Y') ? kDoorYellowLocked : (ch == '"') ? kDoorBlueUnlocked
+                                                                          : kDoorYellowUnlocked;
+        tile = (uint8_t)(kTileDoor | (type << 4) | n_doors);
+        ++n_doors;
+        break;
+      }
+      default:
+        if (ch < '1' || ch > '9') return fail("ascii map has an unknown symbol");
+        tile = (uint8_t)(ch - '1' + 2);
+    }
+    if ((tile & 0x8F) == 0) ++n_floor;
+    grid[row * N + col] = tile;
+    ++col;
+  }
+  if (n_floor == 0) return fail("ascii map has no floor tile");
+  for (int k = 0; k < N; ++k) {
+    const uint8_t e[4] = {grid[k], grid[(N - 1) * N + k], grid[k * N], grid[k * N + N - 1]};
+    for (uint8_t v : e)
+      if ((v & kTileDoor) || (v & 0x0F) == 0) return fail("ascii map border tiles must be walls");
+  }
+  return n_doors;
+}
+
+}  // namespace jx

@@ -116,6 +116,7 @@ struct Client {
   int n = 0;
   jx_env_cfg cfg{};
   std::vector<uint64_t> seeds;
+  std::string ascii;  // copy of the configuration's ASCII map, if any
   // state image (layouts generated on the host at open), uploaded on admission
   std::vector<uint8_t> img;
   std::vector<int32_t> idx;
@@ -592,6 +593,10 @@ jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, co
   auto c = std::make_unique<Client>();
   c->n = n_envs;
   c->cfg = *cfg;
+  if (cfg->ascii_map) {  // the caller's text need not outlive this call
+    c->ascii = cfg->ascii_map;
+    c->cfg.ascii_map = c->ascii.c_str();
+  }
   c->seeds.assign(seeds, seeds + n_envs);
   c->bytes = client_bytes(n_envs, *cfg, &c->L, &c->obs_bytes);
   if (c->bytes > s->budget) return set_error(JX_ENOMEM, "client exceeds the HBM budget on its own");

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjx.so")
 
 JX_OK, JX_EINVAL, JX_ENOMEM, JX_EDEVICE, JX_ESTATE, JX_EBUSY = 0, -1, -2, -3, -4, -5
-ABI_VERSION = 2  # the jx_env_cfg layout this binding marshals
+ABI_VERSION = 3  # the jx_env_cfg layout this binding marshals
 JX_FORM_PLAIN, JX_FORM_PERSISTENT, JX_FORM_PIPELINE = 0, 1, 2
 JX_ROLLOUT_GRAPH, JX_ROLLOUT_FUSED = 1, 2
 JX_SERVE_COALESCE, JX_SERVE_PLAIN = 0, 1
@@ -42,7 +42,8 @@ class jx_env_cfg(ctypes.Structure):
                 ("episode_cap", ctypes.c_int32), ("move", ctypes.c_float),
                 ("turn", ctypes.c_float), ("pickup_radius", ctypes.c_float),
                 ("r_goal", ctypes.c_float), ("r_key", ctypes.c_float),
-                ("shade_levels", ctypes.c_int32), ("shade_dist", ctypes.c_float)]
+                ("shade_levels", ctypes.c_int32), ("shade_dist", ctypes.c_float),
+                ("ascii_map", ctypes.c_char_p)]
 
 
 class jx_launch(ctypes.Structure):
@@ -140,8 +141,14 @@ def check(code: int) -> int:
 
 
 def make_cfg(d: dict) -> jx_env_cfg:
+    """The configuration struct of a dict; "ascii_map" (optional) is a str or
+    None (the struct keeps a reference to the encoded text)."""
     c = jx_env_cfg()
     for name, _ in jx_env_cfg._fields_:
+        if name == "ascii_map":
+            m = d.get("ascii_map")
+            c.ascii_map = None if m is None else m.encode("ascii")
+            continue
         setattr(c, name, d[name])
     return c
 
@@ -348,7 +355,8 @@ _FIELD_DTYPES = {"x": np.float32, "y": np.float32, "theta": np.float32, "t": np.
                  "episode": np.uint32, "goal": np.int32, "door": np.int32, "key": np.int32,
                  "decor": np.int32, "flags": np.uint8, "events": np.uint8, "n_decor": np.uint8,
                  "invalid": np.uint32, "seed": np.uint64, "cfg_index": np.int32,
-                 "map_offset": np.uint32, "obs_offset": np.int64, "order": np.int32}
+                 "map_offset": np.uint32, "obs_offset": np.int64, "order": np.int32,
+                 "akey": np.int32, "doors": np.uint32}
 
 
 def unpack_state(buf: np.ndarray, layout: dict) -> dict:

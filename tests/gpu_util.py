@@ -34,7 +34,8 @@ def env_of(cfgs, seeds, cfg_index=None, obs=True):
 
 
 def oracle_maze(cfg: dict, seed: int) -> np.ndarray:
-    return orc.maze(int(seed), cfg["side"], cfg["loop_frac"])
+    """The env's tile grid as the oracle builds it (ASCII map or seeded maze)."""
+    return orc.layout(cfg, int(seed))
 
 
 def ulp_close(a32, b64, k=2):
@@ -56,13 +57,22 @@ def synth_state(rng, cfg: dict, seed: int, grid: np.ndarray) -> dict:
     st = orc.reset(grid, oc, int(seed), ep).as_dict()
     key_taken = int(rng.integers(0, 2)) if st["key"] >= 0 else 0
     N = cfg["side"]
-    free = np.argwhere(grid == 0)[:, ::-1]                  # (x, y)
+    # ASCII maps: random keys taken and doors open; the pose may be in an open door
+    akey_taken = 0
+    for c in range(3):
+        if st["akey"][c] >= 0 and rng.integers(0, 2):
+            akey_taken |= 1 << c
+    doors_open = int(rng.integers(0, 1 << 16)) if cfg.get("ascii_map") else 0
+    floor = (grid & 0x8F) == 0
+    is_door = (grid & 0x80) != 0
+    open_door = is_door & (((doors_open >> (grid & 15).astype(np.int64)) & 1) == 1)
+    free = np.argwhere(floor | open_door)[:, ::-1]           # (x, y)
     if st["door"] >= 0 and not key_taken:
         free = free[(free[:, 1] * N + free[:, 0]) != st["door"]]
     x, y, th = W.random_poses(rng, free, 1)
     st.update(x=float(x[0]), y=float(y[0]), theta=float(th[0]),
               t=int(rng.integers(0, cfg["episode_cap"])), key_taken=key_taken,
-              door_open=key_taken)
+              door_open=key_taken, akey_taken=akey_taken, doors_open=doors_open)
     return st
 
 
@@ -77,8 +87,11 @@ def gpu_fields(states: list[dict]) -> dict:
          "door": np.array([s["door"] for s in states], np.int32),
          "key": np.array([s["key"] for s in states], np.int32),
          "decor": np.array([list(s["decor"])[:2] for s in states], np.int32).reshape(-1),
-         "flags": np.array([s["key_taken"] | (s["door_open"] << 1) for s in states], np.uint8),
-         "n_decor": np.array([s["n_decor"] for s in states], np.uint8)}
+         "flags": np.array([s["key_taken"] | (s["door_open"] << 1) | (s.get("akey_taken", 0) << 2)
+                            for s in states], np.uint8),
+         "n_decor": np.array([s["n_decor"] for s in states], np.uint8),
+         "akey": np.array([list(s.get("akey", [-1, -1, -1])) for s in states], np.int32).reshape(-1),
+         "doors": np.array([s.get("doors_open", 0) for s in states], np.uint32)}
     assert f["x"].shape == (n,)
     return f
 
@@ -88,10 +101,13 @@ def gpu_state_dict(S: dict, i: int) -> dict:
             "t": int(S["t"][i]), "episode": int(S["episode"][i]), "goal": int(S["goal"][i]),
             "door": int(S["door"][i]), "key": int(S["key"][i]),
             "key_taken": int(S["flags"][i] & 1), "door_open": int((S["flags"][i] >> 1) & 1),
-            "n_decor": int(S["n_decor"][i]), "decor": [int(S["decor"][2 * i]), int(S["decor"][2 * i + 1])]}
+            "n_decor": int(S["n_decor"][i]), "decor": [int(S["decor"][2 * i]), int(S["decor"][2 * i + 1])],
+            "akey": [int(v) for v in S["akey"][3 * i:3 * i + 3]],
+            "akey_taken": int((S["flags"][i] >> 2) & 7), "doors_open": int(S["doors"][i])}
 
 
-EXACT_KEYS = ("t", "episode", "goal", "door", "key", "key_taken", "door_open", "n_decor")
+EXACT_KEYS = ("t", "episode", "goal", "door", "key", "key_taken", "door_open", "n_decor", "akey",
+              "akey_taken", "doors_open")
 
 
 def compare_reset_state(g: dict, o: dict) -> list[str]:

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(jx):
 
 
 def test_abi_version(jx):
-    assert jx.lib().jx_abi_version() == jx.ABI_VERSION == 2
+    assert jx.lib().jx_abi_version() == jx.ABI_VERSION == 3
 
 
 @pytest.mark.parametrize("side", [5, 8, 9, 16, 31, 32, 64])
@@ -111,3 +111,27 @@ def test_binding_checks_buffer_extents():
         jx._need("reward", t[::2], 10)
     with pytest.raises(jx.JxError):
         jx._need("reward", None, 1)
+
+
+@pytest.mark.parametrize("text,side", [(W.MAP16, 16), (W.MAP10, 10), (W.MAP10, 13)])
+def test_host_ascii_layout_equals_oracle(jx, orc, text, side):
+    """The library's ASCII front-end and the oracle's (independent parsers of
+    the Table 2 format) produce the same tile grid."""
+    cfg = W.env_cfg(side=side, ascii_map=text)
+    g_host = jx.make_layout(0, cfg)
+    g_orc, _, _ = orc.ascii_layout(text, side)
+    assert np.array_equal(g_host, g_orc)
+
+
+@pytest.mark.parametrize("text,kw", [
+    ("#####\n#.x.#\n#####", {}),                       # unknown symbol
+    ("#####\n#....\n#####", {"side": 5}),              # border tile (x = 4 of 5) not a wall
+    ("#####\n#.R.#\n#####", {"key_door": 1}),          # generated key-door with a map
+    ("##\"##\n#.R.#\n#####", {"side": 5}),             # a door on the border (row 0)
+    ("#" * 17, {}),                                    # wider than the side
+])
+def test_host_ascii_rejects(jx, text, kw):
+    kw = dict({"side": 16}, **kw)
+    cfg = W.env_cfg(ascii_map=text, **kw)
+    with pytest.raises(jx.JxError):
+        jx.make_layout(0, cfg)

@@ -75,6 +75,24 @@ def test_graph_eager_persistent_identical():
     _forms_equal(cfg, seeds, None, 40, launches)
 
 
+def test_ascii_maps_every_form_identical():
+    """ASCII maps (doors opened by bumps and keys across episodes) mixed with a
+    generated maze in one batch: every launch form gives the same outputs."""
+    cfgs = [W.ASCII["cfg"], W.ASCII_TINY["cfg"], dict(W.ASCII_TINY["cfg"], n_actions=6),
+            W.env_cfg(side=16, loop_frac=0.1, goal_sprite=1, episode_cap=60)]
+    n = 768
+    idx = (np.arange(n) * 7 % 4).astype(np.int32)
+    seeds = W.seeds(61, n)
+    launches = [("eager", PLAIN1),
+                ("graph", dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0)),
+                ("graph", dict(form=1, waves_per_group=2, groups_per_cu=4, store_mode=0)),
+                ("graph", dict(form=2, waves_per_group=2, groups_per_cu=2, store_mode=1)),
+                ("fused", dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0))]
+    ref = _forms_equal(cfgs, seeds, idx, 150, launches)
+    # doors were opened and keys taken along the way
+    assert ref[1].max() >= 0.5
+
+
 def test_fused_rollout_long_and_resets():
     """More than 128 steps (two action windows) across episode ends."""
     cfg = W.env_cfg(side=12, loop_frac=0.1, goal_sprite=1, key_door=1, max_decor=2,

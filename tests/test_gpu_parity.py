@@ -29,7 +29,8 @@ def _dbg_np(buf, env):
                                             ("cell", "<i4")])).reshape(env.n, mw)
 
 
-@pytest.mark.parametrize("wl,n_check", [(W.TINY, 16), (W.SCALE, 96), (W.KEYDOOR, 64)])
+@pytest.mark.parametrize("wl,n_check", [(W.TINY, 16), (W.SCALE, 96), (W.KEYDOOR, 64),
+                                        (W.ASCII, 96), (W.ASCII_TINY, 16)])
 def test_reset_state_and_first_frame(wl, n_check):
     import torch
     cfg = wl["cfg"]
@@ -177,7 +178,8 @@ def _render_case(cfg, n, number, n_check, seed_rng=3, launch=None):
 
 
 @pytest.mark.parametrize("wl,n,n_check", [(W.TINY, 16, 16), (W.SCALE, 4096, 256),
-                                          (W.KEYDOOR, 8192, 160)])
+                                          (W.KEYDOOR, 8192, 160), (W.ASCII, 4096, 256),
+                                          (W.ASCII_TINY, 16, 16)])
 def test_render_shared_state(wl, n, n_check):
     _render_case(wl["cfg"], n, wl["number"], n_check)
 
@@ -202,6 +204,14 @@ def test_one_step_scale_full_size_sampled():
                    launch=dict(form=0, waves_per_group=1, groups_per_cu=4, store_mode=0))
 
 
+def test_one_step_ascii_maps():
+    # every Table 2 symbol: keys by colour, locked and unlocked doors (random
+    # open/taken states), candidates, coloured walls
+    _one_step_case(W.ASCII["cfg"], 4096, W.ASCII["number"], 200, seed_rng=61)
+    for k in range(4):
+        _one_step_case(W.ASCII_TINY["cfg"], 16, W.ASCII_TINY["number"], 16, seed_rng=70 + k)
+
+
 def test_one_step_keydoor_sampled():
     _one_step_case(W.KEYDOOR["cfg"], 8192, W.KEYDOOR["number"], 96)
 
@@ -220,14 +230,15 @@ def test_persistent_form_matches_plain_one_step():
     assert a >= 0
 
 
-def test_trajectory_tiny_full():
-    """The tiny workload end to end: 16 envs x 1000 uniform-random steps, every
-    env every step, GPU and oracle each running its own trajectory from the
-    same seeds and actions.  Outcomes must agree at every step; a step whose
-    outcome differs must be one the oracle flags, with its window widened by the
+@pytest.mark.parametrize("wl", [W.TINY, W.ASCII_TINY])
+def test_trajectory_tiny_full(wl):
+    """A small workload end to end (16 envs, every env every step, 1000 steps on
+    a maze or 400 on the ASCII map), GPU and oracle each running its own
+    trajectory from the same seeds and actions.  Outcomes (reward, done, events,
+    keys taken, doors open) must agree at every step; a step whose outcome
+    differs must be one the oracle flags, with its window widened by the
     measured FP32/FP64 drift (after which that env is no longer compared)."""
     import torch
-    wl = W.TINY
     cfg, n, T = wl["cfg"], wl["n_envs"], wl["steps"]
     seeds = W.seeds(wl["number"], n)
     acts = W.actions(wl["number"], T, n, cfg["n_actions"])
@@ -244,11 +255,14 @@ def test_trajectory_tiny_full():
     ys = np.zeros((T, n), np.float32)
     evs = np.zeros((T, n), np.uint8)
     eps = np.zeros((T, n), np.uint32)
+    fls = np.zeros((T, n), np.uint8)
+    drs = np.zeros((T, n), np.uint32)
     for t in range(T):
         env.step(act_d[t], obs[t * env.obs_bytes:(t + 1) * env.obs_bytes], rew[t * n:(t + 1) * n],
                  done[t * n:(t + 1) * n])
         S = env.get_state()
         xs[t], ys[t], evs[t], eps[t] = S["x"], S["y"], S["events"], S["episode"]
+        fls[t], drs[t] = S["flags"], S["doors"]
     obs_np = obs.cpu().numpy().reshape(T, -1)
     rew_np = rew.cpu().numpy().reshape(T, n)
     done_np = done.cpu().numpy().reshape(T, n)
@@ -261,7 +275,8 @@ def test_trajectory_tiny_full():
                 continue
             nxt, r, d, ev, sf = orc.step(grids[i], oc, int(seeds[i]), ost[i], int(acts[t, i]))
             drift = max(abs(float(xs[t, i]) - nxt.x), abs(float(ys[t, i]) - nxt.y))
-            same = (r == rew_np[t, i] and d == done_np[t, i] and ev == evs[t, i])
+            same = (r == rew_np[t, i] and d == done_np[t, i] and ev == evs[t, i] and
+                    nxt.akey_taken == (fls[t, i] >> 2) & 7 and nxt.doors_open == drs[t, i])
             if not same:
                 prev = 0.0 if t == 0 else max(abs(float(xs[t - 1, i]) - ost[i].x),
                                               abs(float(ys[t - 1, i]) - ost[i].y))

@@ -20,7 +20,7 @@ PI = math.pi
 # Per-environment configuration fields, in the C-ABI struct's order.
 CFG_FIELDS = ("side", "n_colors", "loop_frac", "key_door", "goal_sprite", "max_decor",
               "obs_h", "obs_w", "fov_deg", "n_actions", "episode_cap", "move", "turn",
-              "pickup_radius", "r_goal", "r_key")
+              "pickup_radius", "r_goal", "r_key", "shade_levels", "shade_dist", "ascii_map")
 
 
 def env_cfg(**kw) -> dict:
@@ -35,7 +35,7 @@ def env_cfg(**kw) -> dict:
     return base
 
 
-# The five workloads: (number used to derive seeds, env count, steps, cfg).
+# The workloads: (number used to derive seeds, env count, steps, cfg).
 TINY = dict(number=1, name="tiny-16env-8x8-64px", n_envs=16, steps=1000,
             cfg=env_cfg(side=8, n_colors=4, loop_frac=0.0, n_actions=4, episode_cap=256))
 SCALE = dict(number=2, name="scale-4096env-16x16-64px", n_envs=4096, steps=10_240, warmup=128,
@@ -46,11 +46,56 @@ KEYDOOR = dict(number=3, name="keydoor-8192env-32x32-84px", n_envs=8192, steps=2
                            max_decor=2, obs_h=84, obs_w=84, n_actions=6, episode_cap=1024,
                            r_goal=1.0, r_key=0.5))
 BATCH = dict(number=4, name="batch-16384env-mixed", n_envs=16384, rollout=128)
+# A 16x16 map in the paper's ASCII format (Table 2), written for this
+# repository: five rooms joined by a red-locked, a blue-locked and a yellow-locked
+# door and two unlocked doors, the three keys, spawn and goal candidates and
+# coloured walls.
+MAP16 = "\n".join([
+    "################",
+    "#S....1..#....G#",
+    "#.....1..#.....#",
+    "#..r.....R..y..#",
+    "#.....1..#.....#",
+    '##"#######\\#####',
+    "#......#.......#",
+    "#.2222.#..S....#",
+    "#.2..2.B.......#",
+    "#.2222.#...b...#",
+    "#......#.......#",
+    "####Y#######.###",
+    "#..............#",
+    "#.S.....33...G.#",
+    "#..............#",
+    "################",
+])
+
+# A 10x10 map with every symbol, for oracle-scale trajectories.
+MAP10 = "\n".join([
+    "##########",
+    "#S..1...G#",
+    "#.##1#.#.#",
+    '#..r"..R.#',
+    "####.###.#",
+    "#b..B..\\.#",
+    "#.######.#",
+    "#y...2...#",
+    "#S...9.GY#",
+    "##########",
+])
+
 SERVE = dict(number=5, name="serve-256clients-poisson2000", clients=256, rate=2000.0,
              min_envs=1, max_envs=512, min_side=8, max_side=64, obs=(64, 84),
              mean_session=64)
 
 WORKLOADS = {w["name"]: w for w in (TINY, SCALE, KEYDOOR, BATCH, SERVE)}
+
+
+ASCII = dict(number=6, name="ascii-4096env-16x16-64px", n_envs=4096, steps=2560, warmup=128,
+             cfg=env_cfg(side=16, ascii_map=MAP16, goal_sprite=1, n_actions=6, episode_cap=512,
+                         obs_h=64, obs_w=64))
+ASCII_TINY = dict(number=7, name="ascii-16env-10x10-64px", n_envs=16, steps=400,
+                  cfg=env_cfg(side=10, ascii_map=MAP10, goal_sprite=1, n_actions=4, episode_cap=128,
+                              obs_h=64, obs_w=64))
 
 
 def seeds(number: int, n: int, offset: int = 0) -> np.ndarray:
