@@ -152,6 +152,15 @@ def lib():
         L.orc_rollout.argtypes = [ctypes.POINTER(OrcCfg), ctypes.c_int32, u64p, ctypes.c_int32,
                                   u8p, u8p]
         L.orc_rollout.restype = ctypes.c_int64
+        L.orc_norm_f32.argtypes = [ctypes.c_int32]
+        L.orc_norm_f32.restype = ctypes.c_float
+        L.orc_norm_bf16.argtypes = [ctypes.c_int32]
+        L.orc_norm_bf16.restype = ctypes.c_uint16
+        L.orc_format_frame.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_void_p]
+        L.orc_format_frame.restype = ctypes.c_int64
+        L.orc_prev_action.argtypes = [ctypes.POINTER(OrcCfg), ctypes.c_int32, ctypes.c_int32]
+        L.orc_prev_action.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -278,6 +287,38 @@ def rollout(cfg: OrcCfg, seeds: np.ndarray, actions: np.ndarray, want_obs: bool 
                              _p(actions, ctypes.c_uint8),
                              _p(last, ctypes.c_uint8) if want_obs else None)
     return done, last
+
+
+# ---- training-buffer formats --------------------------------------------------
+OBS_NHWC, OBS_NCHW = 0, 1
+OBS_U8, OBS_BF16, OBS_F32 = 0, 1, 2
+_FMT_NP = {OBS_U8: np.uint8, OBS_BF16: np.uint16, OBS_F32: np.float32}
+
+
+def norm_f32(b: int) -> float:
+    return float(lib().orc_norm_f32(int(b)))
+
+
+def norm_bf16(b: int) -> int:
+    """Bit pattern of b / 255 rounded to bfloat16."""
+    return int(lib().orc_norm_bf16(int(b)))
+
+
+def format_frame(hwc: np.ndarray, layout: int, dtype: int) -> np.ndarray:
+    """The frame hwc[H, W, 3] in a training-buffer format: shape (H, W, 3) for
+    NHWC or (3, H, W) for NCHW; uint8, bfloat16 bit patterns (uint16) or float32."""
+    f = np.ascontiguousarray(hwc, np.uint8)
+    H, W, _ = f.shape
+    out = np.zeros((H, W, 3) if layout == OBS_NHWC else (3, H, W), _FMT_NP[dtype])
+    n = lib().orc_format_frame(_p(f, ctypes.c_uint8), H, W, layout, dtype,
+                               out.ctypes.data_as(ctypes.c_void_p))
+    if n != out.nbytes:
+        raise ValueError("bad format arguments")
+    return out
+
+
+def prev_action(cfg: OrcCfg, action: int, done: int) -> int:
+    return int(lib().orc_prev_action(ctypes.byref(cfg), int(action), int(done)))
 
 
 def tan_half_fov(cfg: OrcCfg) -> float:

@@ -883,3 +883,61 @@ int64_t orc_rollout(const orc_cfg* cfg, int32_t n_envs, const uint64_t* seeds, i
   free(obs);
   return done_steps;
 }
+
+/* ---- training-buffer formats --------------------------------------------
+ * Reading: the learner of the paper's training runs feeds 64x64 frames and the
+ * previous action to a recurrent policy and stores 128-step rollouts (Sec. 3.1,
+ * training hyperparameter table).  The paper does not say how frames are
+ * normalised; this oracle takes the usual division of the byte by 255.  The
+ * quotient is formed in double and rounded once to the target type: the
+ * double of b/255 is itself a rounding, but b and 255 are exact in both
+ * targets and double carries more than twice their precision plus two bits,
+ * so that second rounding equals the direct one (the tests check every byte
+ * against exact fractions). */
+float orc_norm_f32(int32_t b) { return (float)((double)b / 255.0); }
+
+/* Round-to-nearest-even of a double in [0, 1] to bfloat16 (8 significant
+ * bits), done on the exponent and significand directly. */
+uint16_t orc_norm_bf16(int32_t b) {
+  const double q = (double)b / 255.0;
+  if (q == 0.0) return 0;
+  int e;
+  const double m = frexp(q, &e);        /* q = m 2^e, m in [0.5, 1) */
+  const double s = ldexp(m, 8);         /* in [128, 256), exact */
+  const double f = floor(s), r = s - f;
+  uint32_t k = (uint32_t)f;
+  if (r > 0.5 || (r == 0.5 && (k & 1u))) ++k;
+  const float v = (float)ldexp((double)k, e - 8);   /* exact in float */
+  uint32_t bits;
+  memcpy(&bits, &v, 4);
+  return (uint16_t)(bits >> 16);
+}
+
+int64_t orc_format_frame(const uint8_t* hwc, int32_t H, int32_t W, int32_t layout,
+                         int32_t dtype, void* out) {
+  if (!hwc || !out || H <= 0 || W <= 0) return -1;
+  if (layout != ORC_OBS_NHWC && layout != ORC_OBS_NCHW) return -1;
+  if (dtype != ORC_OBS_U8 && dtype != ORC_OBS_BF16 && dtype != ORC_OBS_F32) return -1;
+  const int64_t n = (int64_t)H * W * 3;
+  for (int32_t r = 0; r < H; ++r)
+    for (int32_t c = 0; c < W; ++c)
+      for (int32_t ch = 0; ch < 3; ++ch) {
+        const uint8_t b = hwc[((int64_t)r * W + c) * 3 + ch];
+        const int64_t i = layout == ORC_OBS_NHWC ? ((int64_t)r * W + c) * 3 + ch
+                                                 : ((int64_t)ch * H + r) * W + c;
+        if (dtype == ORC_OBS_U8) ((uint8_t*)out)[i] = b;
+        else if (dtype == ORC_OBS_BF16) ((uint16_t*)out)[i] = orc_norm_bf16(b);
+        else ((float*)out)[i] = orc_norm_f32(b);
+      }
+  return n * (dtype == ORC_OBS_U8 ? 1 : dtype == ORC_OBS_BF16 ? 2 : 4);
+}
+
+/* Reading: the policy sees the action that led to the current frame; a frame
+ * that opens an episode has none, coded as n_actions (one past the last
+ * action, so a one-hot of width n_actions + 1 marks it).  An out-of-range
+ * action moved nothing and is coded the same way. */
+int32_t orc_prev_action(const orc_cfg* cfg, int32_t action, int32_t done) {
+  if (!cfg) return -1;
+  if (done || action < 0 || action >= cfg->n_actions) return cfg->n_actions;
+  return action;
+}

@@ -149,6 +149,28 @@ int32_t orc_cast(const uint8_t* grid, int32_t N, int32_t door, int32_t door_open
                  double x, double y, double rx, double ry,
                  int32_t* side, double* tstar, int32_t* flags);
 
+/* ---- training-buffer formats ------------------------------------------- */
+/* The frames a recurrent-PPO learner consumes (the paper trains on 64x64
+ * frames with 128-step rollouts and the previous action fed to the policy):
+ * layout 0 = NHWC (obs[H][W][3]), 1 = NCHW (obs[3][H][W]); dtype 0 = the
+ * byte itself, 1 = bfloat16, 2 = float32, where the floating types hold the
+ * byte divided by 255 rounded to nearest (ties to even) in that type. */
+#define ORC_OBS_NHWC 0
+#define ORC_OBS_NCHW 1
+#define ORC_OBS_U8   0
+#define ORC_OBS_BF16 1
+#define ORC_OBS_F32  2
+float orc_norm_f32(int32_t b);     /* b / 255 rounded to float32 */
+uint16_t orc_norm_bf16(int32_t b); /* b / 255 rounded to bfloat16 (bit pattern) */
+/* Converts one rendered frame hwc[H][W][3] into `out` in the given format;
+ * returns the bytes written or -1 on bad arguments. */
+int64_t orc_format_frame(const uint8_t* hwc, int32_t H, int32_t W, int32_t layout,
+                         int32_t dtype, void* out);
+/* The previous action stored beside the frame a step returns: the action
+ * taken, or n_actions ("none") when that frame starts an episode or the
+ * action was not a valid one. */
+int32_t orc_prev_action(const orc_cfg* cfg, int32_t action, int32_t done);
+
 /* Runs `n_steps` steps of `n_envs` environments, each from episode 0, with
  * actions[t*n_envs+i], rendering every frame into a scratch buffer.  This is
  * the timed CPU baseline; returns the number of env-steps done. */
