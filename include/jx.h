@@ -20,9 +20,12 @@
  *   - Step, render and rollout are asynchronous on the context's stream and
  *     return after enqueueing; device faults surface as JX_EDEVICE on a later
  *     call or on jx_sync().  A context serves one stream and is not thread-safe.
- *   - Observations are uint8 RGB, row-major [row][col][channel], row 0 at the
- *     top.  With one configuration for all envs the batch is [n][H][W][3]; with
- *     several configurations env i starts at byte offset jx_obs_offsets()[i].
+ *   - Observations are RGB, row 0 at the top, by default uint8 row-major
+ *     [row][col][channel]; jx_env_cfg.obs_layout / obs_dtype select the other
+ *     training-buffer formats (JX_OBS_*).  With one configuration for all envs
+ *     the batch is [n][frame]; with several configurations env i starts at byte
+ *     offset jx_obs_offsets()[i].  Observation pointers and strides are in
+ *     bytes whatever the element type.
  *   - Reward is float32 per env, done is uint8 per env; both belong to the
  *     transition.  When done = 1 the env has been reset inside the step and its
  *     observation is the first frame of the next episode.
@@ -37,7 +40,7 @@
 extern "C" {
 #endif
 
-#define JX_ABI_VERSION 3
+#define JX_ABI_VERSION 4
 
 typedef int32_t jx_status;
 #define JX_OK 0
@@ -91,7 +94,24 @@ typedef struct {
    * and max_decor must be 0.  The text is read by the call that takes the
    * configuration and need not outlive it. */
   const char* ascii_map;
+  /* Frame format, for writing frames straight into a learner's rollout buffer
+   * (the paper trains a recurrent PPO agent on 64x64 frames over 128-step
+   * rollouts, Sec. 3.1 and the training hyperparameters of the appendix).
+   * obs_layout: JX_OBS_NHWC ([H][W][3]) or JX_OBS_NCHW ([3][H][W]).
+   * obs_dtype: JX_OBS_U8 (the byte), JX_OBS_BF16 or JX_OBS_F32 (the byte / 255
+   * rounded to nearest-even in that type; the paper leaves normalisation open,
+   * this is the library's reading).  Every configuration of one context must
+   * use the same format.  Frame bytes = H * W * 3 * element size.  The serving
+   * API takes the default format (NHWC, U8) only. */
+  int32_t obs_layout;
+  int32_t obs_dtype;
 } jx_env_cfg;
+
+#define JX_OBS_NHWC 0
+#define JX_OBS_NCHW 1
+#define JX_OBS_U8 0
+#define JX_OBS_BF16 1
+#define JX_OBS_F32 2
 
 typedef struct jx_ctx jx_ctx;
 
@@ -160,15 +180,20 @@ int64_t jx_obs_bytes(const jx_ctx* ctx);
 jx_status jx_obs_offsets(const jx_ctx* ctx, int64_t* offsets_host);
 
 /* One batched transition and render.  actions_dev[n] uint8 (values >= n_actions
- * are counted no-ops); obs_dev receives jx_obs_bytes() bytes (4-byte aligned);
- * reward_dev[n] float32; done_dev[n] uint8. */
+ * are counted no-ops); obs_dev receives jx_obs_bytes() bytes (4-byte aligned;
+ * 16-byte aligned for the floating formats); reward_dev[n] float32; done_dev[n]
+ * uint8.  prev_action_dev (nullable) [n] uint8 receives the previous action to
+ * feed the policy beside the returned frame (the paper's agent concatenates
+ * it): the action taken, or n_actions ("none") when the frame starts a new
+ * episode (done = 1) or the action was out of range. */
 jx_status jx_step(jx_ctx* ctx, const uint8_t* actions_dev, uint8_t* obs_dev, float* reward_dev,
-                  uint8_t* done_dev);
+                  uint8_t* done_dev, uint8_t* prev_action_dev);
 
 /* T consecutive steps.  actions_dev[T][n]; step t writes its frames at
  * obs_dev + t*obs_stride (obs_stride >= jx_obs_bytes(), or 0 to write every
  * step into the same frame buffer), rewards at reward_dev + t*n, dones at
- * done_dev + t*n.  flags & JX_ROLLOUT_GRAPH: the T launches are captured once
+ * done_dev + t*n and, when prev_action_dev is not NULL, previous actions (as in
+ * jx_step) at prev_action_dev + t*n.  flags & JX_ROLLOUT_GRAPH: the T launches are captured once
  * per (T, launch mapping) into a hipGraph and replayed with one graph launch;
  * the buffers of each call reach the captured kernels through a descriptor in
  * the workspace, so a captured graph serves any buffers.  Without the flag the
@@ -181,7 +206,8 @@ jx_status jx_step(jx_ctx* ctx, const uint8_t* actions_dev, uint8_t* obs_dev, flo
  * mapping's waves_per_group (4 when another form is selected). */
 #define JX_ROLLOUT_FUSED 2
 jx_status jx_rollout(jx_ctx* ctx, int32_t T, const uint8_t* actions_dev, uint8_t* obs_dev,
-                     int64_t obs_stride, float* reward_dev, uint8_t* done_dev, int32_t flags);
+                     int64_t obs_stride, float* reward_dev, uint8_t* done_dev,
+                     uint8_t* prev_action_dev, int32_t flags);
 
 /* Renders the current state without stepping.  obs_dev may be NULL;
  * column_debug_dev (nullable) receives jx_col_debug[n][max obs_w]. */

@@ -78,6 +78,9 @@ bool validate_cfg(const jx_env_cfg& c, std::string* why) {
   if (c.shade_levels < 0 || c.shade_levels > kMaxShadeLevels) return bad("shade_levels must be in 0..16");
   if (c.shade_levels > 0 && !(c.shade_dist > 0.f && std::isfinite(c.shade_dist)))
     return bad("shade_dist must be finite and > 0 when shading is on");
+  if (c.obs_layout != JX_OBS_NHWC && c.obs_layout != JX_OBS_NCHW) return bad("obs_layout must be JX_OBS_NHWC or JX_OBS_NCHW");
+  if (c.obs_dtype != JX_OBS_U8 && c.obs_dtype != JX_OBS_BF16 && c.obs_dtype != JX_OBS_F32)
+    return bad("obs_dtype must be JX_OBS_U8, JX_OBS_BF16 or JX_OBS_F32");
   if (c.ascii_map) {
     if (c.key_door || c.max_decor) return bad("an ascii map brings its own keys and doors: key_door and max_decor must be 0");
     std::vector<uint8_t> g((size_t)c.side * c.side);
@@ -157,6 +160,11 @@ Layout make_layout(int n, int n_cfgs, int64_t maps_bytes) {
 
 int64_t map_bytes_of(int side) { return align_up((int64_t)side * side, 16); }
 
+int obs_fmt_of(const jx_env_cfg& c) { return c.obs_layout * 3 + c.obs_dtype; }
+int64_t frame_bytes(const jx_env_cfg& c) {
+  return (int64_t)c.obs_h * c.obs_w * 3 * obs_elem_bytes(obs_fmt_of(c));
+}
+
 // Marks a batch whose envs all use one configuration (the common case): the
 // kernels then read the configuration from the kernel argument and compute map
 // and frame offsets from the env index.
@@ -172,7 +180,7 @@ void set_uniform(DevState* s, const jx_env_cfg* cfgs, int n_cfgs, const std::vec
   s->uniform = 1;
   s->ucfg = derive_cfg(c);
   s->map_stride = map_bytes_of(c.side);
-  s->obs_stride = (int64_t)c.obs_h * c.obs_w * 3;
+  s->obs_stride = frame_bytes(c);
 }
 
 DevState bind_state(uint8_t* ws, const Layout& L, int n) {
@@ -235,7 +243,7 @@ jx_status build_image(int n, const uint64_t* seeds, const jx_env_cfg* cfgs, int 
   obs_off->assign(n + 1, 0);
   for (int i = 0; i < n; ++i) {
     const jx_env_cfg& c = cfgs[idx[i]];
-    (*obs_off)[i + 1] = (*obs_off)[i] + (int64_t)c.obs_h * c.obs_w * 3;
+    (*obs_off)[i + 1] = (*obs_off)[i] + frame_bytes(c);
   }
   std::memcpy(b + L.seed, seeds, 8 * (size_t)n);
   std::memcpy(b + L.cfg_idx, idx.data(), 4 * (size_t)n);
@@ -373,7 +381,11 @@ jx_status jx_reset(jx_ctx* c, int32_t n_envs, const uint64_t* seeds, const jx_en
   for (int k = 0; k < n_cfgs; ++k) {
     std::string why;
     if (!validate_cfg(cfgs[k], &why)) return set_error(JX_EINVAL, "cfg " + std::to_string(k) + ": " + why);
+    if (obs_fmt_of(cfgs[k]) != obs_fmt_of(cfgs[0]))
+      return set_error(JX_EINVAL, "every configuration must use the same obs_layout and obs_dtype");
   }
+  if (obs_dev && ((uintptr_t)obs_dev & (obs_align(obs_fmt_of(cfgs[0])) - 1)))
+    return set_error(JX_EINVAL, "obs must be 16-byte aligned for the floating formats");
   std::vector<uint8_t> img;
   Layout L;
   std::vector<int64_t> oo;
@@ -409,6 +421,7 @@ jx_status jx_reset(jx_ctx* c, int32_t n_envs, const uint64_t* seeds, const jx_en
     c->max_w = std::max(c->max_w, cfgs[k].obs_w);
   }
   set_uniform(&c->S, cfgs, n_cfgs, idx);
+  c->S.obs_fmt = obs_fmt_of(cfgs[0]);
   DevIo io{};
   io.obs = obs_dev;
   io.mode = MODE_RESET;
@@ -439,38 +452,44 @@ jx_status jx_obs_offsets(const jx_ctx* c, int64_t* offsets_host) {
   return JX_OK;
 }
 
-jx_status jx_step(jx_ctx* c, const uint8_t* actions, uint8_t* obs, float* reward, uint8_t* done) {
+jx_status jx_step(jx_ctx* c, const uint8_t* actions, uint8_t* obs, float* reward, uint8_t* done,
+                  uint8_t* prev_action) {
   jx_status st = check_ready(c);
   if (st) return st;
   if (c->n == 0) return JX_OK;
   if (!actions || !obs || !reward || !done) return set_error(JX_EINVAL, "null buffer");
-  if ((uintptr_t)obs & 3) return set_error(JX_EINVAL, "obs must be 4-byte aligned");
+  if ((uintptr_t)obs & (obs_align(c->S.obs_fmt) - 1))
+    return set_error(JX_EINVAL, "obs must be 4-byte aligned (16-byte for the floating formats)");
   DevIo io{};
   io.act = actions;
   io.obs = obs;
   io.rew = reward;
   io.done = done;
+  io.prev = prev_action;
   io.mode = MODE_STEP;
   io.store_mode = c->launch.store_mode;
   return launch_or_fail(c, io, c->stream);
 }
 
 jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs, int64_t obs_stride,
-                     float* reward, uint8_t* done, int32_t flags) {
+                     float* reward, uint8_t* done, uint8_t* prev_action, int32_t flags) {
   jx_status st = check_ready(c);
   if (st) return st;
   if (T < 0) return set_error(JX_EINVAL, "T < 0");
   if (c->n == 0 || T == 0) return JX_OK;
   if (!actions || !obs || !reward || !done) return set_error(JX_EINVAL, "null buffer");
   const int64_t ob = c->obs_off.back();
-  if (obs_stride < 0 || (obs_stride != 0 && obs_stride < ob) || (obs_stride & 3) || ((uintptr_t)obs & 3))
-    return set_error(JX_EINVAL, "obs_stride must be 0 or >= jx_obs_bytes(), 4-byte aligned");
+  const int al = obs_align(c->S.obs_fmt);
+  if (obs_stride < 0 || (obs_stride != 0 && obs_stride < ob) || (obs_stride & (al - 1)) ||
+      ((uintptr_t)obs & (al - 1)))
+    return set_error(JX_EINVAL, "obs_stride must be 0 or >= jx_obs_bytes(); obs and obs_stride 4-byte aligned "
+                                "(16-byte for the floating formats)");
   HIPCHK(hipSetDevice(c->device));
   if (flags & JX_ROLLOUT_FUSED) {
     LaunchCfg lc = c->launch;
     if (lc.form != JX_FORM_PLAIN || lc.waves_per_group > 8) lc = LaunchCfg{0, 4, 1, lc.store_mode};
-    int rc = launch_rollout_fused(c->S, actions, obs, obs_stride, reward, done, T, lc, c->max_side,
-                                  c->n_cu, c->stream);
+    int rc = launch_rollout_fused(c->S, actions, obs, obs_stride, reward, done, prev_action, T, lc,
+                                  c->max_side, c->n_cu, c->stream);
     if (rc) return set_error(JX_EDEVICE, std::string("fused rollout launch: ") + kernel_error_string(rc));
     return JX_OK;
   }
@@ -481,6 +500,7 @@ jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs,
       io.obs = obs + (int64_t)t * obs_stride;
       io.rew = reward + (int64_t)t * c->n;
       io.done = done + (int64_t)t * c->n;
+      io.prev = prev_action ? prev_action + (int64_t)t * c->n : nullptr;
       io.mode = MODE_STEP;
       io.store_mode = c->launch.store_mode;
       st = launch_or_fail(c, io, c->stream);
@@ -490,7 +510,7 @@ jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs,
   }
   // The captured kernels read their buffers from the workspace descriptor,
   // so one graph per (T, mapping) serves every call.
-  RolloutDesc d{actions, obs, reward, done, obs_stride, c->n, c->launch.store_mode};
+  RolloutDesc d{actions, obs, reward, done, prev_action, obs_stride, c->n, c->launch.store_mode};
   int rc = launch_set_desc(c->S.rdesc, d, c->stream);
   if (rc) return set_error(JX_EDEVICE, std::string("descriptor update: ") + kernel_error_string(rc));
   const std::array<int32_t, 5> key = {T, c->launch.form, c->launch.waves_per_group,
@@ -533,7 +553,8 @@ jx_status jx_render(jx_ctx* c, uint8_t* obs, jx_col_debug* dbg) {
   jx_status st = check_ready(c);
   if (st) return st;
   if (c->n == 0) return JX_OK;
-  if (obs && ((uintptr_t)obs & 3)) return set_error(JX_EINVAL, "obs must be 4-byte aligned");
+  if (obs && ((uintptr_t)obs & (obs_align(c->S.obs_fmt) - 1)))
+    return set_error(JX_EINVAL, "obs must be 4-byte aligned (16-byte for the floating formats)");
   DevIo io{};
   io.obs = obs;
   io.dbg = dbg;

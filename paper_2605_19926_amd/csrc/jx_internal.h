@@ -11,6 +11,10 @@ constexpr int kMaxW = 128;       // column records per wave in LDS
 constexpr int kMaxH = 128;
 constexpr int kMaxDecor = 2;
 constexpr int kMaxShadeLevels = 16;
+// Frame formats: obs_layout * 3 + obs_dtype (layout 0 NHWC, 1 NCHW; dtype 0
+// byte, 1 bfloat16, 2 float32 of byte / 255).
+constexpr int kObsFormats = 6;
+constexpr int obs_elem_bytes(int fmt) { return fmt % 3 == 0 ? 1 : (fmt % 3 == 1 ? 2 : 4); }
 constexpr uint32_t kStateMagic = 0x4A585331u;  // "JXS1"
 
 // Event bits written per env and step.
@@ -57,6 +61,7 @@ struct RolloutDesc {
   uint8_t* obs;
   float* rew;
   uint8_t* done;
+  uint8_t* prev;  // nullable: previous actions, prev + t*n
   int64_t obs_stride;
   int32_t n;
   int32_t store_mode;
@@ -94,6 +99,7 @@ struct DevState {
   // map and frame offsets from the env index (no dependent loads).
   int32_t uniform;
   int32_t any_ascii;  // some configuration is an ASCII map (host-set; picks the kernel variant)
+  int32_t obs_fmt;    // frame format, obs_layout * 3 + obs_dtype (the same for every env)
   DevCfg ucfg;
   int64_t map_stride;
   int64_t obs_stride;
@@ -105,6 +111,7 @@ struct DevIo {
   uint8_t* obs;
   float* rew;
   uint8_t* done;
+  uint8_t* prev;      // nullable: previous action per env
   void* dbg;          // jx_col_debug[n][dbg_stride]
   int32_t dbg_stride;
   int32_t mode;
@@ -141,7 +148,7 @@ int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int 
 int launch_clear_queues(uint32_t* queues, void* stream);
 // One launch for T steps of every env (actions for all steps given up front).
 int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride,
-                         float* rew, uint8_t* dn, int T, const LaunchCfg& lc, int max_side, int n_cu,
+                         float* rew, uint8_t* dn, uint8_t* prev, int T, const LaunchCfg& lc, int max_side, int n_cu,
                          void* stream);
 int launch_set_desc(RolloutDesc* rd_dev, const RolloutDesc& value, void* stream);
 int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeItem* items_dev,

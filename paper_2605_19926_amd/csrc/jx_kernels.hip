@@ -59,6 +59,27 @@ __device__ __forceinline__ void stage_colors(uint32_t* lclr) {
   }
   __syncthreads();
 }
+
+// Training-buffer formats (fmt = layout * 3 + dtype): the floating types hold
+// byte / 255 rounded to nearest-even.  The quotient is an IEEE division in
+// float (correctly rounded); bfloat16 rounds that float to nearest-even, which
+// equals rounding the exact quotient directly because float carries more than
+// twice bfloat16's 8 significant bits plus two.
+template <int DT>
+__device__ __forceinline__ uint32_t norm_entry(uint32_t b) {
+  const uint32_t u = __float_as_uint((float)b / 255.0f);
+  if (DT == 2) return u;
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// Colour table and, for the floating formats, the byte -> element table
+// (256 words), both into the workgroup's LDS.
+template <int FMT>
+__device__ __forceinline__ void stage_tables(uint32_t* lclr, uint32_t* lcvt) {
+  if (FMT % 3 != 0)
+    for (int i = (int)threadIdx.x; i < 256; i += (int)blockDim.x) lcvt[i] = norm_entry<FMT % 3>((uint32_t)i);
+  stage_colors(lclr);
+}
 constexpr uint32_t kCeil = rgb(50, 50, 60);
 constexpr uint32_t kFloor = rgb(90, 80, 70);
 constexpr uint32_t kDoor = rgb(120, 0, 0);
@@ -264,6 +285,10 @@ __device__ Episode episode_reset(const DevCfg& cf, const uint8_t* lmap, uint64_t
 }
 
 typedef __attribute__((address_space(1))) uint32_t GlobalU32;
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) u32x2 GlobalU32x2;
+typedef __attribute__((address_space(1))) u32x4 GlobalU32x4;
 
 // 12 bytes (4 RGB pixels) to global memory; non-temporal on request.
 __device__ __forceinline__ void store12(uint8_t* p, uint32_t a, uint32_t b, uint32_t c, int nt) {
@@ -361,6 +386,155 @@ __device__ __forceinline__ void emit_pair(const ColGroup& g, uint32_t i, uint32_
   const uint32_t x2 = bitsel(perm(sb, sa, kSelMask2), g.ps[2], g.pw[2]);
   store12(up, bitsel(m0, x0, kCeil3[0]), bitsel(m1, x1, kCeil3[1]), bitsel(m2, x2, kCeil3[2]), nt);
   store12(dn, bitsel(m0, x0, kFloor3[0]), bitsel(m1, x1, kFloor3[1]), bitsel(m2, x2, kFloor3[2]), nt);
+}
+
+// ---- training-buffer formats --------------------------------------------------
+// Each lane still covers a group of 4 columns and one mirrored row pair per
+// iteration; it emits kWords dwords per row: contiguous ([row][col][ch]) in
+// NHWC, or kElem dwords into each of the 3 channel planes in NCHW.  Colour
+// words hold converted elements; per-pixel masks come from the same biased
+// counts as the byte format (v_perm sign-bit replication, selector 8 + pixel).
+template <int FMT>
+struct ObsFmt {
+  static constexpr bool kPlanar = FMT >= 3;
+  static constexpr int kDtype = FMT % 3;
+  static constexpr int kElem = kDtype == 0 ? 1 : (kDtype == 1 ? 2 : 4);
+  static constexpr int kWords = 3 * kElem;  // dwords per lane and row
+  static constexpr int kPer = 4 / kElem;    // elements per dword
+  // pixel (0..3 in the group) and channel of element j of dword k
+  static constexpr int pixel(int k, int j) { return kPlanar ? (k % kElem) * kPer + j : (k * kPer + j) / 3; }
+  static constexpr int channel(int k, int j) { return kPlanar ? k / kElem : (k * kPer + j) % 3; }
+  static constexpr uint32_t mask_sel(int k) {
+    uint32_t v = 0;
+    for (int b = 0; b < 4; ++b) v |= (uint32_t)(8 + pixel(k, b / kElem)) << (8 * b);
+    return v;
+  }
+  // byte strides of a frame row, a lane's column group and a channel plane
+  __device__ static int64_t row_bytes(int W) { return (int64_t)(kPlanar ? W : 3 * W) * kElem; }
+  static constexpr int kGroupBytes = (kPlanar ? 4 : 12) * kElem;
+};
+static_assert(ObsFmt<0>::mask_sel(0) == kSelMask0 && ObsFmt<0>::mask_sel(1) == kSelMask1 &&
+                  ObsFmt<0>::mask_sel(2) == kSelMask2, "byte format masks");
+
+template <int FMT>
+struct ColGroupF {
+  uint32_t pw[ObsFmt<FMT>::kWords], ps[ObsFmt<FMT>::kWords];
+  uint32_t cova, covb, sca, scb;
+  uint32_t any;
+};
+
+template <int DT>
+__device__ __forceinline__ uint32_t elem_of(const uint32_t* lcvt, uint32_t b) {
+  return DT == 0 ? b : lcvt[b];
+}
+
+// The kWords dwords of 4 pixels with colours c[0..3] (rgb words).
+template <int FMT>
+__device__ __forceinline__ void pack_words(const uint32_t* lcvt, const uint32_t (&c)[4],
+                                           uint32_t (&out)[ObsFmt<FMT>::kWords]) {
+  using F = ObsFmt<FMT>;
+#pragma unroll
+  for (int k = 0; k < F::kWords; ++k) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < F::kPer; ++j)
+      v |= elem_of<F::kDtype>(lcvt, (c[F::pixel(k, j)] >> (8 * F::channel(k, j))) & 0xFFu) << (8 * F::kElem * j);
+    out[k] = v;
+  }
+}
+
+// The same words for one colour on all 4 pixels, at compile time (the
+// constant evaluator divides with IEEE round-to-nearest-even, as the device
+// does): the ceiling and floor then live in scalar registers.
+template <int DT>
+constexpr uint32_t norm_const(uint32_t b) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, (float)b / 255.0f);
+  return DT == 0 ? b : (DT == 2 ? u : (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+template <int FMT>
+struct BgWords {
+  uint32_t w[ObsFmt<FMT>::kWords];
+};
+template <int FMT>
+constexpr BgWords<FMT> bg_words(uint32_t rgb) {
+  using F = ObsFmt<FMT>;
+  BgWords<FMT> r{};
+  for (int k = 0; k < F::kWords; ++k)
+    for (int j = 0; j < F::kPer; ++j)
+      r.w[k] |= norm_const<F::kDtype>((rgb >> (8 * F::channel(k, j))) & 0xFFu) << (8 * F::kElem * j);
+  return r;
+}
+
+template <int FMT>
+__device__ __forceinline__ ColGroupF<FMT> col_group_f(const uint32_t* lcol, const uint32_t* lcvt, int cq) {
+  const uint4* l4 = reinterpret_cast<const uint4*>(lcol);
+  const uint4 A = l4[2 * cq], B = l4[2 * cq + 1];
+  ColGroupF<FMT> g;
+  const uint32_t w[4] = {A.x, A.z, B.x, B.z}, sp[4] = {A.y, A.w, B.y, B.w};
+  pack_words<FMT>(lcvt, w, g.pw);
+  pack_words<FMT>(lcvt, sp, g.ps);
+  g.cova = perm(A.z, A.x, kSelCount) + kCountBias;
+  g.covb = perm(B.z, B.x, kSelCount) + kCountBias;
+  g.sca = perm(A.w, A.y, kSelCount) + kCountBias;
+  g.scb = perm(B.w, B.y, kSelCount) + kCountBias;
+  const uint32_t a = max(A.x >> 24, A.z >> 24), b = max(B.x >> 24, B.z >> 24);
+  g.any = max(a, b);
+  return g;
+}
+
+// Stores one row's dwords of a lane: p is the lane's place in plane 0.
+template <int FMT>
+__device__ __forceinline__ void store_words(uint8_t* p, int64_t plane, const uint32_t (&v)[ObsFmt<FMT>::kWords],
+                                            int nt) {
+  using F = ObsFmt<FMT>;
+  constexpr int runs = F::kPlanar ? 3 : 1, per = F::kPlanar ? F::kElem : F::kWords;
+#pragma unroll
+  for (int r = 0; r < runs; ++r) {
+    GlobalU32* q = (GlobalU32*)(p + r * plane);
+    if (nt) {
+#pragma unroll
+      for (int k = 0; k < per; ++k) __builtin_nontemporal_store(v[r * per + k], q + k);
+    } else if (per % 4 == 0) {
+#pragma unroll
+      for (int k = 0; k < per; k += 4)
+        *(GlobalU32x4*)(q + k) = u32x4{v[r * per + k], v[r * per + k + 1], v[r * per + k + 2], v[r * per + k + 3]};
+    } else if (per % 2 == 0) {
+#pragma unroll
+      for (int k = 0; k < per; k += 2)
+        *(GlobalU32x2*)(q + k) = u32x2{v[r * per + k], v[r * per + k + 1]};
+    } else {
+#pragma unroll
+      for (int k = 0; k < per; ++k) q[k] = v[r * per + k];
+    }
+  }
+}
+
+// Mirrored row pair at distance i (as emit_pair) in format FMT; cw / fw are
+// the ceiling / floor dwords.
+template <int FMT>
+__device__ __forceinline__ void emit_pair_f(const ColGroupF<FMT>& g, uint32_t i, uint32_t ii, uint8_t* up,
+                                            uint8_t* dn, int64_t plane, int nt) {
+  using F = ObsFmt<FMT>;
+  constexpr BgWords<FMT> cb_ = bg_words<FMT>(kCeil), fb_ = bg_words<FMT>(kFloor);
+  const uint32_t(&cw)[F::kWords] = cb_.w;
+  const uint32_t(&fw)[F::kWords] = fb_.w;
+  if (__ballot(i < g.any) == 0ull) {
+    store_words<FMT>(up, plane, cw, nt);
+    store_words<FMT>(dn, plane, fw, nt);
+    return;
+  }
+  const uint32_t ca = g.cova - ii, cb = g.covb - ii;
+  const uint32_t sa = g.sca - ii, sb = g.scb - ii;
+  uint32_t u[F::kWords], d[F::kWords];
+#pragma unroll
+  for (int k = 0; k < F::kWords; ++k) {
+    const uint32_t m = perm(cb, ca, F::mask_sel(k));
+    const uint32_t x = bitsel(perm(sb, sa, F::mask_sel(k)), g.ps[k], g.pw[k]);
+    u[k] = bitsel(m, x, cw[k]);
+    d[k] = bitsel(m, x, fw[k]);
+  }
+  store_words<FMT>(up, plane, u, nt);
+  store_words<FMT>(dn, plane, d, nt);
 }
 
 struct ColDbg {
@@ -558,7 +732,52 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
 
 // Expands the span records into the frame, one mirrored row pair per lane and
 // iteration: lane -> (column group cq, distance i from the horizon).
-__device__ void fill_frame(const uint32_t* lcol, uint8_t* base, int W, int H, int lane, int nt) {
+template <int FMT>
+__device__ void fill_frame_f(const uint32_t* lcol, const uint32_t* lcvt, uint8_t* base, int W, int H, int lane,
+                             int nt) {
+  using F = ObsFmt<FMT>;
+  const int Q = W >> 2, H2 = H >> 1, G2 = H2 * Q;
+  const int64_t rowb = F::row_bytes(W), plane = (int64_t)H * W * F::kElem;
+  int i = lane / Q, cq = lane - i * Q;
+  const int di = 64 / Q, dq = 64 - di * Q;
+  if (dq == 0) {
+    if (lane < G2) {
+      const ColGroupF<FMT> g = col_group_f<FMT>(lcol, lcvt, cq);
+      uint8_t* up = base + (int64_t)(H2 - 1 - i) * rowb + F::kGroupBytes * cq;
+      uint8_t* dn = base + (int64_t)(H2 + i) * rowb + F::kGroupBytes * cq;
+      const int64_t step = (int64_t)di * rowb;
+      uint32_t ii = (uint32_t)i * kRowStep;
+      const uint32_t dii = (uint32_t)di * kRowStep;
+      for (; i < H2; i += di) {
+        emit_pair_f<FMT>(g, (uint32_t)i, ii, up, dn, plane, nt);
+        ii += dii;
+        up -= step;
+        dn += step;
+      }
+    }
+  } else {
+    for (int k = lane; k < G2; k += 64) {
+      const ColGroupF<FMT> g = col_group_f<FMT>(lcol, lcvt, cq);
+      emit_pair_f<FMT>(g, (uint32_t)i, (uint32_t)i * kRowStep,
+                       base + (int64_t)(H2 - 1 - i) * rowb + F::kGroupBytes * cq,
+                       base + (int64_t)(H2 + i) * rowb + F::kGroupBytes * cq, plane, nt);
+      i += di;
+      cq += dq;
+      if (cq >= Q) {
+        cq -= Q;
+        ++i;
+      }
+    }
+  }
+}
+
+template <int FMT>
+__device__ void fill_frame(const uint32_t* lcol, const uint32_t* lcvt, uint8_t* base, int W, int H, int lane,
+                           int nt) {
+  if constexpr (FMT != 0) {
+    fill_frame_f<FMT>(lcol, lcvt, base, W, H, lane, nt);
+    return;
+  }
   const int Q = W >> 2, H2 = H >> 1, G2 = H2 * Q;
   const int rowb = 3 * W;
   int i = lane / Q, cq = lane - i * Q;
@@ -601,6 +820,7 @@ struct EnvOut {
   int env, W, H, mode;
   float x, y, th, reward;
   uint32_t t, ep, fl, nd, ev, done, doors;
+  uint32_t prev;  // previous action beside the frame (n_actions: none)
   int goal, door, key, dec0, dec1;
 };
 
@@ -706,8 +926,10 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   float sn, cs;
   sincosf(th, &sn, &cs);
   bool heading_changed = false;
+  uint32_t prev = (uint32_t)cf.n_actions;
   if (mode == MODE_STEP) {
     const int a = action >= 0 ? action : io.act[env];
+    if (a < cf.n_actions) prev = (uint32_t)a;
     float mvx = 0.f, mvy = 0.f, dth = 0.f;
     if (a >= cf.n_actions) {
       ev |= EV_INVALID;
@@ -808,6 +1030,7 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
     const bool trunc = t >= (uint32_t)cf.cap;
     if (trunc) ev |= EV_TRUNC;
     done = term || trunc;
+    if (done) prev = (uint32_t)cf.n_actions;
   }
   if (mode == MODE_RESET || done) {
     const uint32_t e = (mode == MODE_RESET) ? 0u : ep + 1u;
@@ -853,6 +1076,7 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   o.dec0 = dec0;
   o.dec1 = dec1;
   o.doors = doors;
+  o.prev = prev;
 }
 
 // Scalar results of one env-step, stored by lane 0 with vector stores.
@@ -877,6 +1101,7 @@ __device__ void write_back(const DevState& S, const DevIo& io, const EnvOut& o, 
   if (o.mode == MODE_STEP) {
     io.rew[env] = o.reward;
     io.done[env] = (uint8_t)o.done;
+    if (io.prev) io.prev[env] = (uint8_t)o.prev;
   }
 }
 
@@ -886,15 +1111,15 @@ __device__ __forceinline__ int64_t obs_off_of(const DevState& S, int env) {
 }
 
 // The whole per-env pipeline in one wave.
-template <int MAXN, bool ASC>
+template <int MAXN, bool ASC, int FMT>
 __device__ __forceinline__ void process_env(const DevState& S, const DevIo& io, int env, int lane, uint8_t* lmap,
-                            const uint32_t* lclr, uint32_t* lcol) {
+                            const uint32_t* lclr, const uint32_t* lcvt, uint32_t* lcol) {
   EnvIn<MAXN> in;
   load_env<MAXN>(S, env, lane, in);
   EnvOut o;
   produce_env<MAXN, true, ASC>(in, S, io, -1, lane, lmap, lclr, lcol, o);
   o.obs_off = obs_off_of(S, env);
-  if (io.obs) fill_frame(lcol, io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
+  if (io.obs) fill_frame<FMT>(lcol, lcvt, io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
   write_back(S, io, o, lane);
 }
 
@@ -907,22 +1132,24 @@ __device__ __forceinline__ DevIo io_of(const DevIo& io, const RolloutDesc* rd, i
   r.obs = rd->obs + (int64_t)t * rd->obs_stride;
   r.rew = rd->rew + (int64_t)t * n;
   r.done = rd->done + (int64_t)t * n;
+  r.prev = rd->prev ? rd->prev + (int64_t)t * n : nullptr;
   r.store_mode = rd->store_mode;
   return r;
 }
 
-template <int MAXN, int WPB, bool ASC>
+template <int MAXN, int WPB, bool ASC, int FMT>
 __global__ __launch_bounds__(64 * WPB) void k_plain(DevState S, DevIo io0, const RolloutDesc* rd,
                                                     int t) {
   __shared__ __align__(16) uint8_t smap[WPB][MAXN * MAXN];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
   __shared__ uint32_t sclr[kColorWords];
-  stage_colors(sclr);
+  __shared__ uint32_t scvt[FMT % 3 ? 256 : 1];
+  stage_tables<FMT>(sclr, scvt);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int env = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + w);
   if (env >= S.n) return;
   const DevIo io = io_of(io0, rd, t);
-  process_env<MAXN, ASC>(S, io, env, lane, smap[w], sclr, scol[w]);
+  process_env<MAXN, ASC, FMT>(S, io, env, lane, smap[w], sclr, scvt, scol[w]);
 }
 
 // Work distribution of the persistent forms.  Items (positions in a work
@@ -993,7 +1220,7 @@ __global__ __launch_bounds__(64 * WPB) void k_persist(DevState S, DevIo io0, con
   const QueueView v = queue_view<WPB>(S.queues, seq, S.n, w, lane);
   queue_drain(v, lane, [&](int pos) {
     const int env = __builtin_amdgcn_readfirstlane(S.order[pos]);
-    process_env<kMaxSide, ASC>(S, io, env, lane, smap[w], sclr, scol[w]);
+    process_env<kMaxSide, ASC, 0>(S, io, env, lane, smap[w], sclr, nullptr, scol[w]);
   });
 }
 
@@ -1014,7 +1241,7 @@ __global__ __launch_bounds__(64 * WPB) void k_serve(const DevState* states, cons
     // fields are read from the descriptors where they are used (scalar loads)
     const DevState& S = states[d];
     const DevIo& io = ios[d];
-    process_env<kMaxSide, true>(S, io, env, lane, smap[w], sclr, scol[w]);
+    process_env<kMaxSide, true, 0>(S, io, env, lane, smap[w], sclr, nullptr, scol[w]);
   });
 }
 
@@ -1062,7 +1289,7 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
     } else if (k > 0) {
       const EnvOut o = sout[pair][b ^ 1];
       if (o.env >= 0) {
-        fill_frame(scol[pair][b ^ 1], io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
+        fill_frame<0>(scol[pair][b ^ 1], nullptr, io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
         write_back(S, io, o, lane);
       }
     }
@@ -1078,14 +1305,15 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
 // stores.  Waves take envs by a static stride over the work order.  Per step
 // the results are those of a single-step launch; the state is written back
 // once, after the last step.
-template <int MAXN, int WPB, bool ASC>
+template <int MAXN, int WPB, bool ASC, int FMT>
 __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* act, uint8_t* obs,
                                                    int64_t obs_stride, float* rew, uint8_t* dn,
-                                                   int T, int store_mode) {
+                                                   uint8_t* prv, int T, int store_mode) {
   __shared__ __align__(16) uint8_t smap[WPB][MAXN * MAXN];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
   __shared__ uint32_t sclr[kColorWords];
-  stage_colors(sclr);
+  __shared__ uint32_t scvt[FMT % 3 ? 256 : 1];
+  stage_tables<FMT>(sclr, scvt);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int waves = (int)gridDim.x * WPB;
   const int64_t n = S.n;
@@ -1124,10 +1352,11 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
         EnvOut o;
         produce_env<MAXN, false, ASC>(in, S, io, a, ln, smap[w], sclr, scol[w], o);
         const int t = t0 + k;
-        fill_frame(scol[w], obs + (int64_t)t * obs_stride + obs_off, o.W, o.H, ln, store_mode);
+        fill_frame<FMT>(scol[w], scvt, obs + (int64_t)t * obs_stride + obs_off, o.W, o.H, ln, store_mode);
         if (lane == 0) {
           rew[(int64_t)t * n + env] = o.reward;
           dn[(int64_t)t * n + env] = (uint8_t)o.done;
+          if (prv) prv[(int64_t)t * n + env] = (uint8_t)o.prev;
         }
         // the carried state is uniform across the wave: keep it in scalar registers
         const uint32_t ev = uniform_u(o.ev);
@@ -1176,18 +1405,29 @@ __global__ void k_set_desc(RolloutDesc* rd, RolloutDesc v) {
   if (threadIdx.x == 0) *rd = v;
 }
 
-template <int MAXN, bool ASC>
+// The training-buffer formats (FMT != 0) are built for 4 waves per workgroup
+// only: the host maps every launch of such a batch to that shape.
+constexpr int kFmtWaves = 4;
+
+template <int MAXN, bool ASC, int FMT>
 int launch_plain_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb,
                    hipStream_t st) {
-  const int grid = (s.n + wpb - 1) / wpb;
-  switch (wpb) {
-    case 1: hipLaunchKernelGGL((k_plain<MAXN, 1, ASC>), dim3(grid), dim3(64), 0, st, s, io, rd, t); break;
-    case 2: hipLaunchKernelGGL((k_plain<MAXN, 2, ASC>), dim3(grid), dim3(128), 0, st, s, io, rd, t); break;
-    case 4: hipLaunchKernelGGL((k_plain<MAXN, 4, ASC>), dim3(grid), dim3(256), 0, st, s, io, rd, t); break;
-    case 8: hipLaunchKernelGGL((k_plain<MAXN, 8, ASC>), dim3(grid), dim3(512), 0, st, s, io, rd, t); break;
-    default: return -1;
+  if constexpr (FMT != 0) {
+    const int grid = (s.n + kFmtWaves - 1) / kFmtWaves;
+    hipLaunchKernelGGL((k_plain<MAXN, kFmtWaves, ASC, FMT>), dim3(grid), dim3(64 * kFmtWaves), 0, st, s, io,
+                       rd, t);
+    return (int)hipGetLastError();
+  } else {
+    const int grid = (s.n + wpb - 1) / wpb;
+    switch (wpb) {
+      case 1: hipLaunchKernelGGL((k_plain<MAXN, 1, ASC, 0>), dim3(grid), dim3(64), 0, st, s, io, rd, t); break;
+      case 2: hipLaunchKernelGGL((k_plain<MAXN, 2, ASC, 0>), dim3(grid), dim3(128), 0, st, s, io, rd, t); break;
+      case 4: hipLaunchKernelGGL((k_plain<MAXN, 4, ASC, 0>), dim3(grid), dim3(256), 0, st, s, io, rd, t); break;
+      case 8: hipLaunchKernelGGL((k_plain<MAXN, 8, ASC, 0>), dim3(grid), dim3(512), 0, st, s, io, rd, t); break;
+      default: return -1;
+    }
+    return (int)hipGetLastError();
   }
-  return (int)hipGetLastError();
 }
 
 }  // namespace
@@ -1197,7 +1437,7 @@ inline bool mode_needs_plain(const DevIo& io, const RolloutDesc* rd) {
   return !rd && (io.mode != MODE_STEP || io.dbg != nullptr || io.obs == nullptr);
 }
 
-template <int MAXN, bool ASC>
+template <int MAXN, bool ASC, int FMT>
 int launch_pipe_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int p, int groups,
                   hipStream_t st) {
   switch (p) {
@@ -1209,17 +1449,23 @@ int launch_pipe_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int
   return (int)hipGetLastError();
 }
 
-template <int MAXN, bool ASC>
+template <int MAXN, bool ASC, int FMT>
 int launch_roll_n(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride, float* rew,
-                  uint8_t* dn, int T, int wpb, int groups, int nt, hipStream_t st) {
-  switch (wpb) {
-    case 1: hipLaunchKernelGGL((k_roll<MAXN, 1, ASC>), dim3(groups), dim3(64), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
-    case 2: hipLaunchKernelGGL((k_roll<MAXN, 2, ASC>), dim3(groups), dim3(128), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
-    case 4: hipLaunchKernelGGL((k_roll<MAXN, 4, ASC>), dim3(groups), dim3(256), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
-    case 8: hipLaunchKernelGGL((k_roll<MAXN, 8, ASC>), dim3(groups), dim3(512), 0, st, s, act, obs, obs_stride, rew, dn, T, nt); break;
-    default: return -1;
+                  uint8_t* dn, uint8_t* pv, int T, int wpb, int groups, int nt, hipStream_t st) {
+  if constexpr (FMT != 0) {
+    hipLaunchKernelGGL((k_roll<MAXN, kFmtWaves, ASC, FMT>), dim3(groups), dim3(64 * kFmtWaves), 0, st, s, act,
+                       obs, obs_stride, rew, dn, pv, T, nt);
+    return (int)hipGetLastError();
+  } else {
+    switch (wpb) {
+      case 1: hipLaunchKernelGGL((k_roll<MAXN, 1, ASC, 0>), dim3(groups), dim3(64), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt); break;
+      case 2: hipLaunchKernelGGL((k_roll<MAXN, 2, ASC, 0>), dim3(groups), dim3(128), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt); break;
+      case 4: hipLaunchKernelGGL((k_roll<MAXN, 4, ASC, 0>), dim3(groups), dim3(256), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt); break;
+      case 8: hipLaunchKernelGGL((k_roll<MAXN, 8, ASC, 0>), dim3(groups), dim3(512), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt); break;
+      default: return -1;
+    }
+    return (int)hipGetLastError();
   }
-  return (int)hipGetLastError();
 }
 
 template <bool ASC>
@@ -1236,36 +1482,49 @@ int launch_persist_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, 
 }
 
 // Picks the kernel variant by the largest map side and by whether the batch
-// holds ASCII maps.
-template <template <int, bool> class L, typename... A>
-int by_shape(const DevState& s, int max_side, A&&... a) {
+// holds ASCII maps (frame format FMT fixed).
+template <template <int, bool, int> class L, int FMT, typename... A>
+int by_shape_f(const DevState& s, int max_side, A&&... a) {
   if (s.any_ascii) {
-    if (max_side <= 16) return L<16, true>::run(s, a...);
-    if (max_side <= 32) return L<32, true>::run(s, a...);
-    return L<64, true>::run(s, a...);
+    if (max_side <= 16) return L<16, true, FMT>::run(s, a...);
+    if (max_side <= 32) return L<32, true, FMT>::run(s, a...);
+    return L<64, true, FMT>::run(s, a...);
   }
-  if (max_side <= 16) return L<16, false>::run(s, a...);
-  if (max_side <= 32) return L<32, false>::run(s, a...);
-  return L<64, false>::run(s, a...);
+  if (max_side <= 16) return L<16, false, FMT>::run(s, a...);
+  if (max_side <= 32) return L<32, false, FMT>::run(s, a...);
+  return L<64, false, FMT>::run(s, a...);
 }
-template <int MAXN, bool ASC>
+// ... and by the batch's frame format
+template <template <int, bool, int> class L, typename... A>
+int by_shape(const DevState& s, int max_side, A&&... a) {
+  switch (s.obs_fmt) {
+    case 0: return by_shape_f<L, 0>(s, max_side, a...);
+    case 1: return by_shape_f<L, 1>(s, max_side, a...);
+    case 2: return by_shape_f<L, 2>(s, max_side, a...);
+    case 3: return by_shape_f<L, 3>(s, max_side, a...);
+    case 4: return by_shape_f<L, 4>(s, max_side, a...);
+    case 5: return by_shape_f<L, 5>(s, max_side, a...);
+    default: return -1;
+  }
+}
+template <int MAXN, bool ASC, int FMT>
 struct PlainL {
   static int run(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb, hipStream_t st) {
-    return launch_plain_n<MAXN, ASC>(s, io, rd, t, wpb, st);
+    return launch_plain_n<MAXN, ASC, FMT>(s, io, rd, t, wpb, st);
   }
 };
-template <int MAXN, bool ASC>
+template <int MAXN, bool ASC, int FMT>
 struct PipeL {
   static int run(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int p, int groups,
                  hipStream_t st) {
-    return launch_pipe_n<MAXN, ASC>(s, io, rd, t, p, groups, st);
+    return launch_pipe_n<MAXN, ASC, FMT>(s, io, rd, t, p, groups, st);
   }
 };
-template <int MAXN, bool ASC>
+template <int MAXN, bool ASC, int FMT>
 struct RollL {
   static int run(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride, float* rew,
-                 uint8_t* dn, int T, int wpb, int groups, int nt, hipStream_t st) {
-    return launch_roll_n<MAXN, ASC>(s, act, obs, obs_stride, rew, dn, T, wpb, groups, nt, st);
+                 uint8_t* dn, uint8_t* pv, int T, int wpb, int groups, int nt, hipStream_t st) {
+    return launch_roll_n<MAXN, ASC, FMT>(s, act, obs, obs_stride, rew, dn, pv, T, wpb, groups, nt, st);
   }
 };
 
@@ -1286,7 +1545,8 @@ int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int 
   if (s.n <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int wpb = lc.waves_per_group;
-  if (lc.form == 0) return by_shape<PlainL>(s, max_side, io, rd, t, wpb, st);
+  // training-buffer formats: plain form only
+  if (lc.form == 0 || s.obs_fmt != 0) return by_shape<PlainL>(s, max_side, io, rd, t, wpb, st);
   if (lc.form == 2) {
     // waves_per_group counts wave pairs (1, 2 or 4) in the pipelined form
     const int p = wpb > 4 ? 4 : wpb;
@@ -1295,7 +1555,7 @@ int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int 
     if (groups > need) groups = need;
     if (groups < 1) groups = 1;
     if (mode_needs_plain(io, rd)) return by_shape<PlainL>(s, 64, io, rd, t, 1, st);
-    return by_shape<PipeL>(s, max_side, io, rd, t, p, groups, st);
+    return by_shape_f<PipeL, 0>(s, max_side, io, rd, t, p, groups, st);
   }
   int groups = n_cu * lc.groups_per_cu;
   const int need = (s.n + wpb - 1) / wpb;
@@ -1320,16 +1580,16 @@ int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeIt
 }
 
 int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride,
-                         float* rew, uint8_t* dn, int T, const LaunchCfg& lc, int max_side, int n_cu,
-                         void* stream) {
+                         float* rew, uint8_t* dn, uint8_t* prev, int T, const LaunchCfg& lc, int max_side,
+                         int n_cu, void* stream) {
   if (s.n <= 0 || T <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int wpb = lc.waves_per_group;
+  const int wpb = s.obs_fmt != 0 ? kFmtWaves : lc.waves_per_group;
   // one wave per env while they fit on the chip (16 waves per CU), else a stride
   int groups = (s.n + wpb - 1) / wpb;
   const int cap = n_cu * (16 / wpb > 0 ? 16 / wpb : 1);
   if (groups > cap) groups = cap;
-  return by_shape<RollL>(s, max_side, act, obs, obs_stride, rew, dn, T, wpb, groups, lc.store_mode, st);
+  return by_shape<RollL>(s, max_side, act, obs, obs_stride, rew, dn, prev, T, wpb, groups, lc.store_mode, st);
 }
 
 const char* kernel_error_string(int code) { return hipGetErrorString((hipError_t)code); }

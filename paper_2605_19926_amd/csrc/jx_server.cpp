@@ -590,6 +590,7 @@ jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, co
   if (n_envs < 1 || n_envs > kMaxItemsPerLaunch) return set_error(JX_EINVAL, "n_envs out of range");
   std::string why;
   if (!validate_cfg(*cfg, &why)) return set_error(JX_EINVAL, why);
+  if (obs_fmt_of(*cfg) != 0) return set_error(JX_EINVAL, "serving takes the default frame format (NHWC, U8) only");
   auto c = std::make_unique<Client>();
   c->n = n_envs;
   c->cfg = *cfg;

@@ -17,10 +17,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjx.so")
 
 JX_OK, JX_EINVAL, JX_ENOMEM, JX_EDEVICE, JX_ESTATE, JX_EBUSY = 0, -1, -2, -3, -4, -5
-ABI_VERSION = 3  # the jx_env_cfg layout this binding marshals
+ABI_VERSION = 4  # the jx_env_cfg layout and signatures this binding marshals
 JX_FORM_PLAIN, JX_FORM_PERSISTENT, JX_FORM_PIPELINE = 0, 1, 2
 JX_ROLLOUT_GRAPH, JX_ROLLOUT_FUSED = 1, 2
 JX_SERVE_COALESCE, JX_SERVE_PLAIN = 0, 1
+JX_OBS_NHWC, JX_OBS_NCHW = 0, 1
+JX_OBS_U8, JX_OBS_BF16, JX_OBS_F32 = 0, 1, 2
+OBS_ELEM_BYTES = {JX_OBS_U8: 1, JX_OBS_BF16: 2, JX_OBS_F32: 4}
 
 EV_BLOCKED_X, EV_BLOCKED_Y, EV_KEY, EV_GOAL = 0x01, 0x02, 0x04, 0x08
 EV_TRUNC, EV_INVALID, EV_RESET = 0x10, 0x20, 0x40
@@ -43,7 +46,8 @@ class jx_env_cfg(ctypes.Structure):
                 ("turn", ctypes.c_float), ("pickup_radius", ctypes.c_float),
                 ("r_goal", ctypes.c_float), ("r_key", ctypes.c_float),
                 ("shade_levels", ctypes.c_int32), ("shade_dist", ctypes.c_float),
-                ("ascii_map", ctypes.c_char_p)]
+                ("ascii_map", ctypes.c_char_p),
+                ("obs_layout", ctypes.c_int32), ("obs_dtype", ctypes.c_int32)]
 
 
 class jx_launch(ctypes.Structure):
@@ -87,8 +91,8 @@ _SIGS = {
     "jx_num_envs": (_i32, [_vp]),
     "jx_obs_bytes": (_i64, [_vp]),
     "jx_obs_offsets": (_i32, [_vp, _vp]),
-    "jx_step": (_i32, [_vp, _vp, _vp, _vp, _vp]),
-    "jx_rollout": (_i32, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32]),
+    "jx_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "jx_rollout": (_i32, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32]),
     "jx_render": (_i32, [_vp, _vp, _vp]),
     "jx_state_bytes": (_sz, [_vp]),
     "jx_state_layout": (_i32, [_vp, ctypes.POINTER(jx_field), _i32, ctypes.POINTER(_i32)]),
@@ -149,8 +153,16 @@ def make_cfg(d: dict) -> jx_env_cfg:
             m = d.get("ascii_map")
             c.ascii_map = None if m is None else m.encode("ascii")
             continue
+        if name in ("obs_layout", "obs_dtype"):
+            setattr(c, name, d.get(name, 0))
+            continue
         setattr(c, name, d[name])
     return c
+
+
+def frame_bytes(d: dict) -> int:
+    """Bytes of one frame of configuration d in its format."""
+    return d["obs_h"] * d["obs_w"] * 3 * OBS_ELEM_BYTES[d.get("obs_dtype", JX_OBS_U8)]
 
 
 def _ptr(t) -> int | None:
@@ -232,7 +244,7 @@ class Env:
     def reset(self, obs=None):
         torch = self.torch
         if obs is not None:
-            per_cfg = [c["obs_h"] * c["obs_w"] * 3 for c in self.cfgs]
+            per_cfg = [frame_bytes(c) for c in self.cfgs]
             need = (per_cfg[0] * self.n if self.cfg_index is None
                     else int(sum(per_cfg[i] for i in self.cfg_index)))
             _need("obs", obs, need, self.dev)
@@ -266,29 +278,35 @@ class Env:
         if obs is not None and self._reset_done:
             _need(name, obs, self.obs_bytes, self.dev)
 
-    def step(self, actions, obs, reward=None, done=None):
+    def step(self, actions, obs, reward=None, done=None, prev=None):
+        """One step; prev (optional uint8 [n]) receives the previous action to
+        feed the policy beside each returned frame (n_actions at an episode start)."""
         reward = self.reward if reward is None else reward
         done = self.done if done is None else done
         _need("actions", actions, self.n, self.dev)
         _need("reward", reward, 4 * self.n, self.dev)
         _need("done", done, self.n, self.dev)
+        if prev is not None:
+            _need("prev", prev, self.n, self.dev)
         self._check_frame(obs)
-        check(lib().jx_step(self.ctx, _ptr(actions), _ptr(obs), _ptr(reward), _ptr(done)))
+        check(lib().jx_step(self.ctx, _ptr(actions), _ptr(obs), _ptr(reward), _ptr(done), _ptr(prev)))
         return reward, done
 
     def rollout(self, actions, obs, reward, done, T: int, obs_stride: int = 0, graph: bool = True,
-                fused: bool = False):
+                fused: bool = False, prev=None):
         flags = (JX_ROLLOUT_GRAPH if graph else 0) | (JX_ROLLOUT_FUSED if fused else 0)
         if T > 0:
             _need("actions", actions, T * self.n, self.dev)
             _need("reward", reward, 4 * T * self.n, self.dev)
             _need("done", done, T * self.n, self.dev)
+            if prev is not None:
+                _need("prev", prev, T * self.n, self.dev)
             if obs_stride and obs_stride < self.obs_bytes:
                 raise JxError(JX_EINVAL, f"obs_stride {obs_stride} < frame bytes {self.obs_bytes}")
             if obs is not None:
                 _need("obs", obs, (T - 1) * obs_stride + self.obs_bytes, self.dev)
         check(lib().jx_rollout(self.ctx, T, _ptr(actions), _ptr(obs), obs_stride, _ptr(reward),
-                               _ptr(done), flags))
+                               _ptr(done), _ptr(prev), flags))
 
     def render(self, obs=None, debug=None):
         self._check_frame(obs)

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(jx):
 
 
 def test_abi_version(jx):
-    assert jx.lib().jx_abi_version() == jx.ABI_VERSION == 3
+    assert jx.lib().jx_abi_version() == jx.ABI_VERSION == 4
 
 
 @pytest.mark.parametrize("side", [5, 8, 9, 16, 31, 32, 64])
@@ -60,7 +60,8 @@ def test_workload_seeds_layouts_match(jx, orc):
 @pytest.mark.parametrize("bad", [dict(side=4), dict(side=65), dict(n_colors=0), dict(n_colors=9),
                                  dict(loop_frac=1.5), dict(max_decor=3), dict(obs_h=3),
                                  dict(obs_w=6), dict(obs_w=132), dict(n_actions=5),
-                                 dict(episode_cap=0), dict(fov_deg=180.0), dict(move=1.0)])
+                                 dict(episode_cap=0), dict(fov_deg=180.0), dict(move=1.0),
+                                 dict(obs_layout=2), dict(obs_layout=-1), dict(obs_dtype=3)])
 def test_layout_rejects_bad_cfg(jx, bad):
     cfg = W.env_cfg(**bad)
     with pytest.raises(jx.JxError) as e:
@@ -90,7 +91,7 @@ def test_workspace_bytes(jx):
 
 def test_null_arguments_are_errors(jx):
     L = jx.lib()
-    assert L.jx_step(None, None, None, None, None) == jx.JX_EINVAL
+    assert L.jx_step(None, None, None, None, None, None) == jx.JX_EINVAL
     assert L.jx_reset(None, 1, None, None, 1, None, None) == jx.JX_EINVAL
     assert L.jx_make_layout(1, None, None) == jx.JX_EINVAL
     assert L.jx_server_submit(None, 0, None, None) == jx.JX_EINVAL

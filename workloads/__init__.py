@@ -20,14 +20,15 @@ PI = math.pi
 # Per-environment configuration fields, in the C-ABI struct's order.
 CFG_FIELDS = ("side", "n_colors", "loop_frac", "key_door", "goal_sprite", "max_decor",
               "obs_h", "obs_w", "fov_deg", "n_actions", "episode_cap", "move", "turn",
-              "pickup_radius", "r_goal", "r_key", "shade_levels", "shade_dist", "ascii_map")
+              "pickup_radius", "r_goal", "r_key", "shade_levels", "shade_dist", "ascii_map",
+              "obs_layout", "obs_dtype")
 
 
 def env_cfg(**kw) -> dict:
     base = dict(side=16, n_colors=8, loop_frac=0.0, key_door=0, goal_sprite=0, max_decor=0,
                 obs_h=64, obs_w=64, fov_deg=60.0, n_actions=6, episode_cap=512, move=0.1,
                 turn=PI / 16, pickup_radius=0.3, r_goal=1.0, r_key=0.5, shade_levels=0,
-                shade_dist=8.0, ascii_map=None)
+                shade_dist=8.0, ascii_map=None, obs_layout=0, obs_dtype=0)
     for k in kw:
         if k not in base:
             raise KeyError(k)
