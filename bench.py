@@ -450,7 +450,45 @@ def main() -> int:
         progress(f"{name}: {n * Kv / vs:.4g} env-steps/s")
         return {"steps": Kv, "env_steps_per_s": n * Kv / vs, "ms_per_step": vs / Kv * 1e3}
 
-    shaded = ascii_maps = None
+    def buffer_rate(layout, dtype):
+        """Fused 128-step rollouts writing a learner's rollout buffer in a
+        training format (frames [128][n][frame], previous actions beside),
+        the buffer reused by every rollout, same workload; one 128-step window
+        of actions serves every rollout."""
+        bcfg = dict(cfg, obs_layout=layout, obs_dtype=dtype)
+        benv = jx.Env(seeds, bcfg)
+        benv.reset()
+        fb = benv.obs_bytes
+        T = 128
+        dev = benv.dev
+        bacts = torch.from_numpy(W.actions(wl["number"] + 100, T, n, cfg["n_actions"])).to(dev)
+        buf = torch.empty(T * fb, dtype=torch.uint8, device=dev)
+        brew = torch.empty(T * n, dtype=torch.float32, device=dev)
+        bdone = torch.empty(T * n, dtype=torch.uint8, device=dev)
+        bprev = torch.empty(T * n, dtype=torch.uint8, device=dev)
+        Kb = max(T, min(K, 1280) // T * T)
+
+        def brun(first, count):
+            for _ in range(first, first + count, T):
+                benv.rollout(bacts, buf, brew, bdone, T, obs_stride=fb, graph=False, fused=True, prev=bprev)
+        brun(0, T)
+        torch.cuda.synchronize()
+        b0, b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b0.record(stream)
+        brun(T, Kb)
+        b1.record(stream)
+        torch.cuda.synchronize()
+        bs = b0.elapsed_time(b1) / 1e3
+        benv.close()
+        del buf
+        r = n * Kb / bs
+        name = f"{['NHWC', 'NCHW'][layout]}-{['u8', 'bf16', 'f32'][dtype]}"
+        progress(f"training buffer {name}: {r:.4g} env-steps/s")
+        return {"format": name, "steps": Kb, "env_steps_per_s": r, "ms_per_step": bs / Kb * 1e3,
+                "frame_bytes": fb // n, "obs_gbs": fb * Kb / bs / 1e9,
+                "frac_of_hbm_peak": fb * Kb / bs / 1e9 / HBM_PEAK_GBS}
+
+    shaded = ascii_maps = buffers = None
     if args.form == "fused" and slots > 1:
         # distance-shaded walls (render option), same workload
         shaded = dict(shade_levels=8, shade_dist=12.0,
@@ -459,6 +497,9 @@ def main() -> int:
         # candidates), same env count and frame size
         ascii_maps = dict(workload=W.ASCII["name"],
                           **variant_rate(W.ASCII["cfg"], W.seeds(W.ASCII["number"], n), "ascii"))
+        # frames written straight into a learner's rollout buffer (with the
+        # previous actions): NCHW float32 and u8, NHWC bfloat16
+        buffers = [buffer_rate(1, 2), buffer_rate(0, 1), buffer_rate(1, 0)]
     S = env.get_state()
     line = {
         "metric": "rendered env-steps/s @4096 envs 64x64 RGB; served p50/p99 step latency vs plain",
@@ -491,6 +532,7 @@ def main() -> int:
         "single_slot": single,
         "distance_shading": shaded,
         "ascii_maps": ascii_maps,
+        "training_buffer": buffers,
         "obs_write_gbs": ab["obs"] * n * K / sec / 1e9,
         "episodes_completed": int(S["episode"].astype(np.int64).sum()),
         "wall_s": wall,
