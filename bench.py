@@ -432,6 +432,7 @@ def main() -> int:
         frame ring (same frame size), timed like the headline."""
         venv = jx.Env(vseeds, vcfg)
         venv.reset(obs[:ob])
+        venv.set_launch(**launch)   # the headline's mapping
         Kv = min(K, 2560)
 
         def vrun(first, count):

@@ -730,6 +730,13 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
   wave_sync();
 }
 
+// s_waitcnt immediate: vector-memory count 4, the other counters untouched.
+// After each row pair a wave waits until at most 4 of its stores (two row
+// pairs) are in flight: on the 4096-env rollout the HBM write stream measured
+// about 1% faster with this bound than with the step-level bound alone (and
+// 2% slower with 8 or 12 in flight at the step level).
+constexpr int kWaitTwoPairs = 0x0F74;
+
 // Expands the span records into the frame, one mirrored row pair per lane and
 // iteration: lane -> (column group cq, distance i from the horizon).
 template <int FMT>
@@ -793,6 +800,7 @@ __device__ void fill_frame(const uint32_t* lcol, const uint32_t* lcvt, uint8_t* 
       const uint32_t dii = (uint32_t)di * kRowStep;
       for (; i < H2; i += di) {
         emit_pair(g, (uint32_t)i, ii, up, dn, nt);
+        __builtin_amdgcn_s_waitcnt(kWaitTwoPairs);
         ii += dii;
         up -= step;
         dn += step;
@@ -803,6 +811,7 @@ __device__ void fill_frame(const uint32_t* lcol, const uint32_t* lcvt, uint8_t* 
       const ColGroup g = col_group(lcol, cq);
       emit_pair(g, (uint32_t)i, (uint32_t)i * kRowStep, base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq,
                 base + (int64_t)(H2 + i) * rowb + 12 * cq, nt);
+      __builtin_amdgcn_s_waitcnt(kWaitTwoPairs);
       i += di;
       cq += dq;
       if (cq >= Q) {
