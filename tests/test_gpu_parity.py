@@ -199,7 +199,8 @@ def test_one_step_tiny_all_envs():
 
 
 def test_one_step_scale_full_size_sampled():
-    # the headline workload's full batch, in the benchmark's launch mapping
+    # the headline workload's full batch, plain per-step mapping (the timed
+    # fused launch is checked by test_headline_fused_rollout_full_size)
     _one_step_case(W.SCALE["cfg"], 4096, W.SCALE["number"], 160,
                    launch=dict(form=0, waves_per_group=1, groups_per_cu=4, store_mode=0))
 
@@ -228,6 +229,84 @@ def test_persistent_form_matches_plain_one_step():
     a, _ = _one_step_case(W.SCALE["cfg"], 1024, 2, 64,
                           launch=dict(form=1, waves_per_group=2, groups_per_cu=2, store_mode=1))
     assert a >= 0
+
+
+def test_headline_fused_rollout_full_size():
+    """The benchmark's timed configuration itself: the 4096 envs of the headline
+    workload in one fused 128-step launch with 8 waves per workgroup, frames into
+    a 128-slot ring.  (a) Every output equals 128 single-step launches from the
+    same start bit for bit (each ring slot compared on the device, every reward
+    and done, the final state); (b) along those single steps a sample of 32 envs
+    is checked against the oracle at every step from the shared state (outcomes
+    exact, positions within 2 ulp, frames bit-exact on unflagged columns)."""
+    import torch
+    wl = W.SCALE
+    cfg, n, T = wl["cfg"], wl["n_envs"], 128
+    H, W_ = cfg["obs_h"], cfg["obs_w"]
+    seeds = W.seeds(wl["number"], n)
+    acts = W.actions(wl["number"], T, n, cfg["n_actions"])
+    env = U.env_of(cfg, seeds, obs=False)
+    env.set_launch(form=0, waves_per_group=8, groups_per_cu=4, store_mode=0)
+    snap = env.get_state_bytes()
+    ob = env.obs_bytes
+    act_d = torch.from_numpy(acts).to(env.dev)
+    ring = torch.empty(T * ob, dtype=torch.uint8, device=env.dev)
+    rew = torch.empty(T * n, dtype=torch.float32, device=env.dev)
+    done = torch.empty(T * n, dtype=torch.uint8, device=env.dev)
+    env.rollout(act_d, ring, rew, done, T, obs_stride=ob, graph=False, fused=True)
+    torch.cuda.synchronize()
+    fused_state = env.get_state_bytes()
+    f_rew, f_done = rew.cpu().numpy(), done.cpu().numpy()
+    # the same steps one launch at a time, from the same start
+    env.set_state_bytes(snap)
+    one = torch.empty(ob, dtype=torch.uint8, device=env.dev)
+    r1 = torch.empty(n, dtype=torch.float32, device=env.dev)
+    d1 = torch.empty(n, dtype=torch.uint8, device=env.dev)
+    rng = np.random.default_rng(5)
+    pick = [int(i) for i in np.sort(rng.choice(n, 32, replace=False))]
+    grids = {i: U.oracle_maze(cfg, seeds[i]) for i in pick}
+    oc = orc.make_cfg(cfg)
+    S_prev = env.get_state()
+    stats = U.FrameStats()
+    skipped = rounding = checked = n_done = 0
+    errors = []
+    for t in range(T):
+        env.step(act_d[t], one, r1, d1)
+        torch.cuda.synchronize()
+        assert torch.equal(one, ring[t * ob:(t + 1) * ob]), f"step {t}: fused frames differ"
+        r_np, d_np = r1.cpu().numpy(), d1.cpu().numpy()
+        assert np.array_equal(r_np, f_rew[t * n:(t + 1) * n]), f"step {t}: rewards differ"
+        assert np.array_equal(d_np, f_done[t * n:(t + 1) * n]), f"step {t}: dones differ"
+        S = env.get_state()
+        one_np = one.cpu().numpy()
+        for i in pick:
+            checked += 1
+            g_after = U.gpu_state_dict(S, i)
+            skip, errs, o = U.compare_step(U.gpu_state_dict(S_prev, i), cfg, seeds[i], grids[i],
+                                           acts[t, i], g_after, r_np[i], d_np[i], S["events"][i])
+            if skip:
+                skipped += 1
+                continue
+            errors += [f"step {t} env {i}: {e}" for e in errs]
+            if errs:
+                continue
+            n_done += int(d_np[i])
+            o32 = U.round32(o)
+            if not U.same_pose(g_after, o32):
+                rounding += 1
+                continue
+            oo, cols = orc.render(grids[i], oc, orc.state_from(o32))
+            U.compare_frame(stats, U.frame_of(one_np, env.obs_offsets, i, H, W_), oo, cols,
+                            tag=f"step {t} env {i}")
+        S_prev = S
+    assert np.array_equal(env.get_state_bytes(), fused_state), "final state differs"
+    assert not errors, errors[:10]
+    assert skipped <= max(2, checked // 50), f"too many flagged steps: {skipped}"
+    assert rounding <= max(3, checked // 10), f"poses one rounding apart: {rounding}"
+    assert not stats.mismatch, stats.mismatch[:10]
+    assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
+    assert stats.cols >= 0.8 * checked * W_
+    env.close()
 
 
 @pytest.mark.parametrize("wl", [W.TINY, W.ASCII_TINY])
