@@ -57,10 +57,18 @@ def algorithmic_bytes(cfg: dict, steps_per_launch: int = 1) -> dict:
             "total": per_step + once / T}
 
 
-def _kernel_source_digest() -> str:
+def _kernel_source_digest(text: str | None = None) -> str:
+    """sha256 (first 16 hex digits) of the kernel source's code, with comments
+    removed and white space collapsed: a comment edit keeps the digest, any
+    code edit changes it."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2605_19926_amd", "csrc", "jx_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    import re
+    if text is None:
+        with open(os.path.join(ROOT, "paper_2605_19926_amd", "csrc", "jx_kernels.hip")) as f:
+            text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()[:16]
 
 
 def measured_traffic(form: str, digest: str):

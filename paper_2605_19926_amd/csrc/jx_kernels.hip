@@ -15,7 +15,9 @@
 //      covering sprite's colour and half-height (billboard sprites, Fig. 1);
 //   5. expand the span records straight into row-major uint8 RGB: each lane
 //      emits 4 consecutive pixels (12 bytes) per iteration, so a wave writes 768
-//      contiguous bytes per store instruction.
+//      contiguous bytes per store instruction.  The training-buffer formats
+//      (NCHW planes, byte / 255 as bfloat16 or float32) expand the same records
+//      into converted elements.
 // Nothing here is a dense contraction, so there is no MFMA; the bound is the
 // HBM write of the frames and the vector ALU of the span expansion.
 #include <hip/hip_runtime.h>
