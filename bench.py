@@ -186,55 +186,17 @@ def serve_form(jx, n_requests: int, mode: int, rate: float = W.SERVE["rate"],
     """Serving workload: Poisson arrivals over 256 client slots, clients of
     1-512 envs (log-uniform), side 8-64, frames 64 or 84 square.  Every client is
     opened before the clock starts (with a tight budget most of them queue for
-    admission); an arrival thread submits each request at its trace time and
-    closes a client right after its last request; four collector threads take
-    completed requests in completion order and copy their frames, rewards and
-    dones to host memory.  Latency is submit-to-ready as measured by the
-    server."""
-    import threading
+    admission).  The library's native load generator (jx_server_replay) submits
+    each request at its trace time, closes a client right after its last
+    request, and collects completed requests in completion order from four
+    threads, copying their frames, rewards and dones to host memory.  Latency
+    is submit-to-ready as measured by the server."""
     tr = W.serve_trace(n_requests, rate=rate)
     srv = jx.Server(hbm_budget=budget, n_streams=n_streams, mode=mode)
     sessions = {}
     last_of = {}
     for k, sid in enumerate(tr["session"]):
         last_of[int(sid)] = k
-    lat = []
-    env_steps = [0]
-    t_done = [0.0]
-    failure = []
-
-    left = [n_requests]
-    lock = threading.Lock()
-    max_n = int(tr["n_envs"].max())
-    max_fb = int(tr["obs"].max()) ** 2 * 3
-
-    def collector():
-        # collects requests in completion order (as independent clients would),
-        # copying each one's frames, rewards and dones into this thread's host
-        # buffers (allocated once, at the largest client's size)
-        mine = (np.empty(max_n * max_fb, np.uint8), np.empty(max_n, np.float32),
-                np.empty(max_n, np.uint8))
-        deadline = time.perf_counter() + 600.0
-        while True:
-            with lock:
-                if left[0] == 0 or failure:
-                    return
-                left[0] -= 1
-            got = None
-            while got is None:
-                if time.perf_counter() > deadline:
-                    failure.append("serving run did not complete within 600 s")
-                    return
-                got = srv.wait_any(timeout=1.0)
-            cid, tk = got
-            n, fb = srv.sizes[cid]
-            out = (mine[0][:n * fb], mine[1][:n], mine[2][:n])
-            res = srv.wait(cid, tk, out=out)
-            with lock:
-                lat.append(res[3])
-                env_steps[0] += res[1].shape[0]
-                t_done[0] = max(t_done[0], time.perf_counter())
-
     queued = 0
     for k in range(n_requests):
         sid = int(tr["session"][k])
@@ -247,43 +209,20 @@ def serve_form(jx, n_requests: int, mode: int, rate: float = W.SERVE["rate"],
             cid, admitted = srv.open(seeds, cfg)
             queued += 0 if admitted else 1
             sessions[sid] = (cid, n)
-    # everything the arrival loop needs is prepared before the clock
+    # everything the replay needs is prepared before the clock
     rng = np.random.default_rng(11)
-    plan = []
-    for k in range(n_requests):
-        sid = int(tr["session"][k])
-        cid, n = sessions[sid]
-        plan.append((float(tr["t"][k]), cid, rng.integers(0, 6, size=n, dtype=np.uint8),
-                     last_of[sid] == k))
-    ths = [threading.Thread(target=collector) for _ in range(4)]
-    old_switch = sys.getswitchinterval()
-    sys.setswitchinterval(1e-4)   # the threads hand the interpreter over often
-    for th in ths:
-        th.start()
-    t0 = time.perf_counter()
-    for t_arr, cid, acts, last in plan:
-        while True:  # sleep for long gaps, spin for short ones
-            wait = t0 + t_arr - time.perf_counter()
-            if wait <= 0:
-                break
-            if wait > 3e-4:
-                time.sleep(wait - 2e-4)
-        srv.submit(cid, acts)
-        if last:
-            srv.close_client(cid)
-    t_submitted = time.perf_counter() - t0
-    for th in ths:
-        th.join()
-    sys.setswitchinterval(old_switch)
-    if failure:
-        raise RuntimeError(failure[0])
+    cids = np.array([sessions[int(s)][0] for s in tr["session"]], np.int32)
+    acts = [rng.integers(0, 6, size=sessions[int(s)][1], dtype=np.uint8) for s in tr["session"]]
+    close_after = np.array([last_of[int(s)] == k for k, s in enumerate(tr["session"])], np.uint8)
+    lat, t_submitted, wall = srv.replay(tr["t"], cids, acts, close_after, n_collectors=4, timeout=600.0)
     progress(f"serving {'coalesced' if mode == jx.JX_SERVE_COALESCE else 'plain'} "
              f"rate {rate:g}/s budget {budget} done")
-    wall = t_done[0] - t0
     st = srv.stats()
     srv.close()
-    lat_ms = np.array(lat) * 1e3
+    lat_ms = lat * 1e3
+    env_steps = int(sum(sessions[int(s)][1] for s in tr["session"]))
     return {"mode": "coalesced" if mode == jx.JX_SERVE_COALESCE else "plain-per-request",
+            "driver": "native replay (jx_server_replay), 4 collector threads",
             "streams": n_streams if mode == jx.JX_SERVE_COALESCE else 1,
             "offered_req_per_s": rate, "submitted_req_per_s": n_requests / t_submitted,
             "hbm_budget_bytes": budget,
@@ -291,7 +230,7 @@ def serve_form(jx, n_requests: int, mode: int, rate: float = W.SERVE["rate"],
             "clients_queued_for_admission": queued,
             "p50_ms": float(np.percentile(lat_ms, 50)),
             "p99_ms": float(np.percentile(lat_ms, 99)), "mean_ms": float(lat_ms.mean()),
-            "env_steps_per_s": env_steps[0] / wall, "launches": int(st["launches"]),
+            "env_steps_per_s": env_steps / wall, "launches": int(st["launches"]),
             "wall_s": wall}
 
 
@@ -562,7 +501,7 @@ def main() -> int:
                      serve_form(jx, nr, jx.JX_SERVE_PLAIN),
                      serve_form(jx, nr, jx.JX_SERVE_COALESCE, rate=8 * W.SERVE["rate"]),
                      serve_form(jx, nr, jx.JX_SERVE_PLAIN, rate=8 * W.SERVE["rate"]),
-                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, budget=256 << 20)]}
+                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, budget=24 << 20)]}
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle on the host cores)")
         line["cpu_baseline"] = cpu_baseline(wl)

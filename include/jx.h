@@ -257,9 +257,11 @@ typedef struct jx_server jx_server;
 #define JX_SERVE_COALESCE 0  /* mode: coalesce ready requests into shared launches */
 #define JX_SERVE_PLAIN 1     /* mode: one launch per request, FIFO, one stream */
 
-/* hbm_budget_bytes bounds the device memory of admitted clients' state, maps
- * and I/O buffers.  n_streams 1..8.  max_batch_envs bounds envs per launch
- * (0 = no bound). */
+/* hbm_budget_bytes bounds the device memory of admitted clients' state and
+ * maps.  Each stream also holds a 128 MiB device staging buffer for its
+ * launches (descriptors, actions, results), and the server a pinned host arena
+ * of min(budget, 2 GiB) mirroring it; one step of a client must fit both.
+ * n_streams 1..8.  max_batch_envs bounds envs per launch (0 = no bound). */
 jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_bytes,
                            int32_t n_streams, int32_t mode, int32_t max_batch_envs);
 void jx_server_destroy(jx_server* srv);
@@ -286,10 +288,10 @@ jx_status jx_server_wait(jx_server* srv, uint64_t ticket, double timeout_s, uint
 /* Completion queue: waits (timeout_s < 0: forever; 0: poll, JX_EBUSY if none)
  * for a completed request not yet collected and returns its ticket and client
  * (client nullable), in completion order, each once.  It does not collect the
- * request: pass the ticket to jx_server_wait.  A request's results occupy the
- * server's pinned staging memory (min(budget, 2 GiB)) from its launch until it
- * is collected, and a request is launched only when its results fit, so
- * callers should collect what completes. */
+ * request: pass the ticket to jx_server_wait.  A launch's results occupy the
+ * server's pinned staging arena (min(budget, 2 GiB)) until every request of
+ * that launch is collected, and a launch is issued only when its results fit,
+ * so callers should collect what completes. */
 jx_status jx_server_wait_any(jx_server* srv, double timeout_s, uint64_t* ticket, int32_t* client);
 
 /* Releases the client once its queued requests have completed; a client still
@@ -310,6 +312,23 @@ typedef struct {
   int64_t clients_pending;
 } jx_server_stats;
 jx_status jx_server_get_stats(jx_server* srv, jx_server_stats* out);
+
+/* Load generator (native threads, so the caller's interpreter does not limit
+ * the offered load): replays an arrival trace against srv.  Request k is
+ * submitted t_arrival_s[k] seconds after the call starts (the trace must be in
+ * arrival order) for client[k] with actions_host[k] (that client's n actions);
+ * if close_after is not NULL and close_after[k] != 0 the client is closed right
+ * after that submit.  n_collectors threads (1..64) take completed requests in
+ * completion order (jx_server_wait_any) and collect them (jx_server_wait) into
+ * buffers of their own.  latency_s[k] receives request k's submit-to-ready
+ * latency; submitted_s (nullable) the time the submits took; wall_s (nullable)
+ * the time until the last result was collected.  Every client of the trace must
+ * be open (admitted or queued).  Returns JX_EDEVICE if a request fails or the
+ * replay exceeds timeout_s (> 0). */
+jx_status jx_server_replay(jx_server* srv, int32_t n, const double* t_arrival_s, const int32_t* client,
+                           const uint8_t* const* actions_host, const uint8_t* close_after,
+                           int32_t n_collectors, double timeout_s, double* latency_s,
+                           double* submitted_s, double* wall_s);
 
 #ifdef __cplusplus
 }

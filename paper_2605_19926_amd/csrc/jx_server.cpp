@@ -8,10 +8,14 @@
 //   admitter        admits queued clients in FIFO order as the HBM budget
 //                   allows: upload of the state image and the episode-0 reset
 //   scheduler       packs every ready request (its client has no step in
-//                   flight, its results fit the staging arena) into one launch
-//                   on the next free stream: H2D actions, descriptors, work
-//                   items; the serving kernel; D2H frames/rewards/dones into
-//                   the request's range of the pinned staging arena; an event
+//                   flight, its results fit the staging buffers) into one
+//                   launch on the next free stream.  A launch's descriptors,
+//                   work items, actions and results sit in one range of that
+//                   stream's device staging buffer, mirrored by one range of
+//                   the pinned host arena, so a launch is one H2D copy, the
+//                   serving kernel, one D2H copy and an event, whatever the
+//                   number of clients in it; the HIP calls are made without
+//                   the server lock
 //   completion      polls the in-flight launches and retires each as it
 //                   completes (any stream order), stamping its requests
 // A caller's wait copies a request's results out of the staging arena and
@@ -21,6 +25,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -89,15 +94,19 @@ class Arena {
   int64_t used_ = 0;
 };
 
+// One launch's range of the pinned host arena, shared by its requests and
+// released when the last of them is collected.
+struct StageRange {
+  int64_t off = -1, len = 0;
+  int left = 0;  // requests not yet collected
+};
+
 struct Request {
   uint64_t ticket = 0;
   int client = -1;
   std::vector<uint8_t> actions;
-  // range of the pinned staging arena, reserved when the request is launched:
-  // actions | frames | rewards | dones (each 256-byte aligned); released when
-  // the caller collects the request
-  int64_t h_off = -1, h_len = 0;
-  uint8_t* h_act = nullptr;
+  // results inside the launch's pinned range (set when the request is launched)
+  std::shared_ptr<StageRange> range;
   uint8_t* h_obs = nullptr;
   float* h_rew = nullptr;
   uint8_t* h_done = nullptr;
@@ -127,7 +136,6 @@ struct Client {
   int64_t arena_off = -1, bytes = 0;
   Layout L{};
   DevState S{};
-  DevIo io{};
   int64_t obs_bytes = 0;
   std::deque<std::shared_ptr<Request>> queue;
 };
@@ -141,19 +149,17 @@ struct Launch {
 struct StreamSlot {
   hipStream_t s = nullptr;
   bool busy = false;
-  DevState* d_states = nullptr;
-  DevIo* d_ios = nullptr;
-  ServeItem* d_items = nullptr;
+  uint8_t* d_stage = nullptr;       // launch staging: descriptors, items, actions, results
   uint32_t* d_counters = nullptr;   // queue counter sets of this stream
   uint32_t seq = 0;                  // serving launches issued on this stream
-  DevState* h_states = nullptr;
-  DevIo* h_ios = nullptr;
-  ServeItem* h_items = nullptr;
   hipEvent_t ev = nullptr;
 };
 
 constexpr int kMaxClientsPerLaunch = 1024;
 constexpr int kMaxItemsPerLaunch = 1 << 18;
+// Device staging per stream slot (outside the HBM budget, which covers the
+// clients' resident state).
+constexpr int64_t kSlotStageBytes = int64_t(128) << 20;
 
 }  // namespace
 
@@ -197,33 +203,63 @@ struct jx_server {
 
 namespace {
 
-// Device bytes of a client: workspace, frames, actions, rewards, dones.
+// Device bytes of a client (its workspace: state and maps); its frames,
+// actions, rewards and dones live in the launch staging.
 int64_t client_bytes(int n, const jx_env_cfg& cfg, Layout* L, int64_t* obs_bytes) {
   *L = make_layout(n, 1, (int64_t)n * map_bytes_of(cfg.side));
   *obs_bytes = (int64_t)n * cfg.obs_h * cfg.obs_w * 3;
-  return align256(L->total) + align256(*obs_bytes) + align256(n) + align256(4 * (int64_t)n) +
-         align256(n);
+  return align256(L->total);
+}
+
+// Offsets (identical in the device staging and the pinned range) of one
+// launch: descriptors | work items | actions | results, each 256-byte aligned.
+struct LaunchPlan {
+  int64_t states = 0, ios = 0, items = 0, acts = 0, results = 0, total = 0;
+  std::vector<int64_t> act, obs, rew, done;
+};
+
+LaunchPlan plan_launch(const std::vector<Client*>& batch) {
+  LaunchPlan P;
+  int64_t o = 0, n_items = 0;
+  for (Client* c : batch) n_items += c->n;
+  P.states = o;
+  o += align256((int64_t)sizeof(DevState) * (int64_t)batch.size());
+  P.ios = o;
+  o += align256((int64_t)sizeof(DevIo) * (int64_t)batch.size());
+  P.items = o;
+  o += align256((int64_t)sizeof(ServeItem) * n_items);
+  P.acts = o;
+  for (Client* c : batch) {
+    P.act.push_back(o);
+    o += align256(c->n);
+  }
+  P.results = o;
+  for (Client* c : batch) {
+    P.obs.push_back(o);
+    o += align256(c->obs_bytes);
+    P.rew.push_back(o);
+    o += align256(4 * (int64_t)c->n);
+    P.done.push_back(o);
+    o += align256(c->n);
+  }
+  P.total = o;
+  return P;
+}
+
+// Upper bound of what one more client adds to a launch's staging.
+int64_t stage_bound(const Client* c) {
+  return align256(sizeof(DevState)) + align256(sizeof(DevIo)) + align256(8 * (int64_t)c->n) +
+         2 * align256(c->n) + align256(c->obs_bytes) + align256(4 * (int64_t)c->n);
 }
 
 // Uploads the client's image (built at open) and runs the episode-0 reset.
 // Called without the server lock; the client's arena range is already reserved.
 jx_status activate(jx_server* s, Client* c) {
   const Layout L = c->L;
-  uint8_t* base = s->arena_base + c->arena_off;
-  uint8_t* ws = base;
-  uint8_t* obs = ws + align256(L.total);
-  uint8_t* act = obs + align256(c->obs_bytes);
-  uint8_t* rew = act + align256(c->n);
-  uint8_t* dn = rew + align256(4 * (int64_t)c->n);
+  uint8_t* ws = s->arena_base + c->arena_off;
   c->L = L;
   c->S = bind_state(ws, L, c->n);
   set_uniform(&c->S, &c->cfg, 1, c->idx);
-  c->io = DevIo{};
-  c->io.act = act;
-  c->io.obs = obs;
-  c->io.rew = (float*)rew;
-  c->io.done = dn;
-  c->io.mode = MODE_STEP;
   if (hipMemcpyAsync(ws, c->img.data(), c->img.size(), hipMemcpyHostToDevice, s->admin) != hipSuccess)
     return set_error(JX_EDEVICE, "client upload failed");
   DevIo io{};
@@ -240,16 +276,12 @@ void free_client_memory(jx_server* s, Client* c) {
   c->arena_off = -1;
 }
 
-// Staging bytes of one request of a client: actions, frames, rewards, dones.
-int64_t staging_bytes(int n, int64_t obs_bytes) {
-  return align256(n) + align256(obs_bytes) + align256(4 * (int64_t)n) + align256(n);
-}
-
-// Returns a request's staging range to the arena (lock held).
+// A request is collected: its launch's pinned range goes back to the arena
+// with the last of the launch's requests (lock held).
 void release_staging(jx_server* s, Request* r) {
-  if (r->h_off >= 0) s->host.release(r->h_off, r->h_len);
-  r->h_off = -1;
-  r->h_act = r->h_obs = r->h_done = nullptr;
+  if (r->range && --r->range->left == 0) s->host.release(r->range->off, r->range->len);
+  r->range.reset();
+  r->h_obs = r->h_done = nullptr;
   r->h_rew = nullptr;
 }
 
@@ -315,64 +347,85 @@ void reap_closed(jx_server* s) {
   }
 }
 
-// Builds and issues one launch on stream slot k from the ready clients.
-void issue(jx_server* s, int k, std::vector<Client*>& batch, const std::vector<int64_t>& stage) {
+// Builds and issues one launch on stream slot k from the batch, whose pinned
+// range (at host_off, plan P) is already reserved.  Called with the lock held;
+// the HIP calls run without it (the slot is marked busy and the clients in
+// flight first, so nothing else touches them meanwhile).
+void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vector<Client*>& batch,
+           const LaunchPlan& P, int64_t host_off) {
   StreamSlot& ss = s->streams[k];
   Launch L;
   L.stream = k;
   L.ev = ss.ev;
+  uint8_t* h = s->host_base + host_off;
+  uint8_t* d = ss.d_stage;
+  auto range = std::make_shared<StageRange>();
+  range->off = host_off;
+  range->len = P.total;
+  range->left = (int)batch.size();
+  std::vector<DevState> states(batch.size());
   int n_items = 0;
-  for (size_t d = 0; d < batch.size(); ++d) {
-    Client* c = batch[d];
+  for (size_t j = 0; j < batch.size(); ++j) {
+    Client* c = batch[j];
     std::shared_ptr<Request> r = c->queue.front();
     c->queue.pop_front();
     c->in_flight = true;
     r->status = 1;
     r->n = c->n;
     r->obs_bytes = c->obs_bytes;
-    r->h_off = stage[d];
-    r->h_len = staging_bytes(c->n, c->obs_bytes);
-    uint8_t* h = s->host_base + r->h_off;
-    r->h_act = h;
-    r->h_obs = h + align256(c->n);
-    r->h_rew = (float*)(r->h_obs + align256(c->obs_bytes));
-    r->h_done = (uint8_t*)r->h_rew + align256(4 * (int64_t)c->n);
+    r->range = range;
+    r->h_obs = h + P.obs[j];
+    r->h_rew = (float*)(h + P.rew[j]);
+    r->h_done = h + P.done[j];
     L.reqs.push_back(r);
-    std::memcpy(r->h_act, r->actions.data(), c->n);
-    ss.h_states[d] = c->S;
-    ss.h_ios[d] = c->io;
-    for (int e = 0; e < c->n; ++e) ss.h_items[n_items++] = ServeItem{(int32_t)d, e};
+    states[j] = c->S;
+    n_items += c->n;
+  }
+  ss.busy = true;
+  const bool plain = s->mode == JX_SERVE_PLAIN;
+  const int side = batch[0]->cfg.side;
+  lk.unlock();
+  // descriptors, work items and actions into the pinned range
+  DevIo* ios = reinterpret_cast<DevIo*>(h + P.ios);
+  ServeItem* items = reinterpret_cast<ServeItem*>(h + P.items);
+  int it = 0;
+  for (size_t j = 0; j < batch.size(); ++j) {
+    Request* r = L.reqs[j].get();
+    std::memcpy(h + P.act[j], r->actions.data(), (size_t)r->n);
+    DevIo io{};
+    io.mode = MODE_STEP;
+    io.act = d + P.act[j];
+    io.obs = d + P.obs[j];
+    io.rew = reinterpret_cast<float*>(d + P.rew[j]);
+    io.done = d + P.done[j];
+    ios[j] = io;
+    if (!plain)
+      for (int e = 0; e < r->n; ++e) items[it++] = ServeItem{(int32_t)j, e};
   }
   hipStream_t st = ss.s;
-  bool ok = true;
-  for (size_t d = 0; d < batch.size(); ++d)
-    ok = ok && hipMemcpyAsync((void*)batch[d]->io.act, L.reqs[d]->h_act, batch[d]->n,
-                              hipMemcpyHostToDevice, st) == hipSuccess;
-  if (s->mode == JX_SERVE_PLAIN) {
-    Client* c = batch[0];
-    ok = ok && launch_batch(c->S, c->io, nullptr, 0, LaunchCfg{0, 1, 1, 0}, c->cfg.side, s->n_cu, 0, st) == 0;
+  bool ok;
+  if (plain) {  // the per-request kernel takes its state and I/O by value: copy the actions only
+    ok = hipMemcpyAsync(d + P.acts, h + P.acts, (size_t)(P.results - P.acts), hipMemcpyHostToDevice, st) ==
+         hipSuccess;
   } else {
-    ok = ok && hipMemcpyAsync(ss.d_states, ss.h_states, sizeof(DevState) * batch.size(),
-                              hipMemcpyHostToDevice, st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(ss.d_ios, ss.h_ios, sizeof(DevIo) * batch.size(), hipMemcpyHostToDevice,
-                              st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(ss.d_items, ss.h_items, sizeof(ServeItem) * n_items, hipMemcpyHostToDevice,
-                              st) == hipSuccess;
+    std::memcpy(h + P.states, states.data(), sizeof(DevState) * states.size());
+    ok = hipMemcpyAsync(d, h, (size_t)P.results, hipMemcpyHostToDevice, st) == hipSuccess;
+  }
+  if (plain) {
+    ok = ok && launch_batch(states[0], ios[0], nullptr, 0, LaunchCfg{0, 1, 1, 0}, side, s->n_cu, 0, st) == 0;
+  } else {
     const int wpb = 2;
     int groups = std::min((n_items + wpb - 1) / wpb, s->n_cu * 4);
     groups = std::max(groups, 1);
-    ok = ok && launch_serve(ss.d_states, ss.d_ios, ss.d_items, n_items, ss.d_counters, ss.seq, wpb,
+    ok = ok && launch_serve(reinterpret_cast<DevState*>(d + P.states), reinterpret_cast<DevIo*>(d + P.ios),
+                            reinterpret_cast<ServeItem*>(d + P.items), n_items, ss.d_counters, ss.seq, wpb,
                             groups, st) == 0;
-    if (ok) ss.seq += 1;
   }
-  for (size_t d = 0; d < batch.size(); ++d) {
-    Client* c = batch[d];
-    Request* r = L.reqs[d].get();
-    ok = ok && hipMemcpyAsync(r->h_obs, c->io.obs, c->obs_bytes, hipMemcpyDeviceToHost, st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(r->h_rew, c->io.rew, 4 * (size_t)c->n, hipMemcpyDeviceToHost, st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(r->h_done, c->io.done, c->n, hipMemcpyDeviceToHost, st) == hipSuccess;
-  }
+  ok = ok && hipMemcpyAsync(h + P.results, d + P.results, (size_t)(P.total - P.results), hipMemcpyDeviceToHost,
+                            st) == hipSuccess;
   ok = ok && hipEventRecord(ss.ev, st) == hipSuccess;
+  lk.lock();
+  if (!plain && ok) ss.seq += 1;
   if (!ok) {
     s->fatal = "launch failed";
     for (auto& r : L.reqs) {
@@ -380,10 +433,10 @@ void issue(jx_server* s, int k, std::vector<Client*>& batch, const std::vector<i
       s->completed.emplace_back(r->ticket, r->client);
     }
     for (Client* c : batch) c->in_flight = false;
+    ss.busy = false;
     s->cv_done.notify_all();
     return;
   }
-  ss.busy = true;
   s->stats.launches += 1;
   s->stats.env_steps += n_items;
   s->inflight.push_back(std::move(L));
@@ -417,26 +470,33 @@ void scheduler_main(jx_server* s) {
       return a->queue.front()->ticket < b->queue.front()->ticket;
     });
     std::vector<Client*> batch;
-    std::vector<int64_t> stage;
     int envs = 0;
+    int64_t bound = 0;
     for (Client* c : ready) {
       if (s->mode == JX_SERVE_PLAIN && !batch.empty()) break;
       if (!batch.empty() && s->max_batch_envs > 0 && envs + c->n > s->max_batch_envs) continue;
       if ((int)batch.size() >= kMaxClientsPerLaunch || envs + c->n > kMaxItemsPerLaunch) break;
-      // results must fit the staging arena; else the request waits for a
-      // caller to collect earlier results
-      const int64_t off = s->host.alloc(staging_bytes(c->n, c->obs_bytes));
-      if (off < 0) continue;
+      if (bound + stage_bound(c) > kSlotStageBytes) continue;
       batch.push_back(c);
-      stage.push_back(off);
       envs += c->n;
+      bound += stage_bound(c);
+    }
+    // the launch's results must fit the pinned arena; else it shrinks, and a
+    // single request that does not fit waits for callers to collect results
+    LaunchPlan P;
+    int64_t off = -1;
+    while (!batch.empty()) {
+      P = plan_launch(batch);
+      off = s->host.alloc(P.total);
+      if (off >= 0) break;
+      batch.resize(batch.size() / 2);
     }
     if (batch.empty()) {
       s->cv_sched.wait(lk);
       continue;
     }
     s->next_stream = (k + 1) % (int)s->streams.size();
-    issue(s, k, batch, stage);
+    issue(s, lk, k, batch, P, off);
   }
 }
 
@@ -535,14 +595,9 @@ jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_by
   for (auto& ss : s->streams) {
     SRV_CHK(hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking), "stream");
     SRV_CHK(hipEventCreateWithFlags(&ss.ev, hipEventDisableTiming), "event");
-    SRV_CHK(hipMalloc((void**)&ss.d_states, sizeof(DevState) * kMaxClientsPerLaunch), "alloc");
-    SRV_CHK(hipMalloc((void**)&ss.d_ios, sizeof(DevIo) * kMaxClientsPerLaunch), "alloc");
-    SRV_CHK(hipMalloc((void**)&ss.d_items, sizeof(ServeItem) * kMaxItemsPerLaunch), "alloc");
+    SRV_CHK(hipMalloc((void**)&ss.d_stage, (size_t)kSlotStageBytes), "staging allocation failed");
     SRV_CHK(hipMalloc((void**)&ss.d_counters, 4 * kQueueWords), "alloc");
     SRV_CHK(hipMemset(ss.d_counters, 0, 4 * kQueueWords), "memset");
-    SRV_CHK(hipHostMalloc((void**)&ss.h_states, sizeof(DevState) * kMaxClientsPerLaunch), "pinned");
-    SRV_CHK(hipHostMalloc((void**)&ss.h_ios, sizeof(DevIo) * kMaxClientsPerLaunch), "pinned");
-    SRV_CHK(hipHostMalloc((void**)&ss.h_items, sizeof(ServeItem) * kMaxItemsPerLaunch), "pinned");
   }
   SRV_CHK(hipDeviceSynchronize(), "sync");
   s->sched = std::thread(scheduler_main, s);
@@ -571,13 +626,8 @@ void jx_server_destroy(jx_server* s) {
   for (auto& ss : s->streams) {
     if (ss.s) hipStreamDestroy(ss.s);
     if (ss.ev) hipEventDestroy(ss.ev);
-    if (ss.d_states) hipFree(ss.d_states);
-    if (ss.d_ios) hipFree(ss.d_ios);
-    if (ss.d_items) hipFree(ss.d_items);
+    if (ss.d_stage) hipFree(ss.d_stage);
     if (ss.d_counters) hipFree(ss.d_counters);
-    if (ss.h_states) hipHostFree(ss.h_states);
-    if (ss.h_ios) hipHostFree(ss.h_ios);
-    if (ss.h_items) hipHostFree(ss.h_items);
   }
   if (s->admin) hipStreamDestroy(s->admin);
   if (s->arena_base) hipFree(s->arena_base);
@@ -601,8 +651,12 @@ jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, co
   c->seeds.assign(seeds, seeds + n_envs);
   c->bytes = client_bytes(n_envs, *cfg, &c->L, &c->obs_bytes);
   if (c->bytes > s->budget) return set_error(JX_ENOMEM, "client exceeds the HBM budget on its own");
-  if (staging_bytes(n_envs, c->obs_bytes) > s->host_bytes)
-    return set_error(JX_ENOMEM, "client's step results exceed the pinned staging arena");
+  {
+    const int64_t one = plan_launch(std::vector<Client*>{c.get()}).total;
+    if (one > kSlotStageBytes || one > s->host_bytes)
+      return set_error(JX_ENOMEM, "one step of this client exceeds the launch staging (" +
+                                      std::to_string(std::min(kSlotStageBytes, s->host_bytes)) + " bytes)");
+  }
   {
     // layouts are generated here, on the caller's thread, so that admission
     // only uploads and resets
@@ -745,6 +799,100 @@ jx_status jx_server_close(jx_server* s, int32_t client) {
     c->closing = true;
   }
   s->cv_sched.notify_one();
+  return JX_OK;
+}
+
+jx_status jx_server_replay(jx_server* s, int32_t n, const double* t_arrival_s, const int32_t* client,
+                           const uint8_t* const* actions_host, const uint8_t* close_after,
+                           int32_t n_collectors, double timeout_s, double* latency_s, double* submitted_s,
+                           double* wall_s) {
+  if (!s || n < 0 || (n > 0 && (!t_arrival_s || !client || !actions_host || !latency_s)))
+    return set_error(JX_EINVAL, "null argument");
+  if (n_collectors < 1 || n_collectors > 64) return set_error(JX_EINVAL, "n_collectors must be in 1..64");
+  if (n == 0) return JX_OK;
+  // result buffers of each collector, sized for the largest client of the trace
+  int64_t max_n = 1, max_obs = 1;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    for (int32_t k = 0; k < n; ++k) {
+      auto it = s->clients.find(client[k]);
+      if (it == s->clients.end()) return set_error(JX_EINVAL, "trace names a client that is not open");
+      max_n = std::max<int64_t>(max_n, it->second->n);
+      max_obs = std::max<int64_t>(max_obs, it->second->obs_bytes);
+    }
+  }
+  std::vector<uint64_t> ticket_of(n, 0);
+  std::atomic<int32_t> left(n);
+  std::atomic<bool> failed(false);
+  std::mutex err_mu;
+  std::string err;
+  std::vector<std::vector<std::pair<uint64_t, double>>> got(n_collectors);
+  std::atomic<double> t_last(0.0);
+  const double t0 = now_s();
+  const double deadline = t0 + (timeout_s > 0 ? timeout_s : 1e30);
+  auto fail = [&](const std::string& m) {
+    std::lock_guard<std::mutex> g(err_mu);
+    if (err.empty()) err = m;
+    failed = true;
+  };
+  auto collector = [&](int id) {
+    std::vector<uint8_t> obs((size_t)max_obs);
+    std::vector<float> rew((size_t)max_n);
+    std::vector<uint8_t> dn((size_t)max_n);
+    while (!failed && left.fetch_sub(1) > 0) {
+      uint64_t tk = 0;
+      int32_t cid = -1;
+      jx_status st = JX_EBUSY;
+      while (st == JX_EBUSY && !failed) {
+        if (now_s() > deadline) {
+          fail("replay did not complete within the timeout");
+          return;
+        }
+        st = jx_server_wait_any(s, 0.05, &tk, &cid);
+      }
+      if (failed) return;
+      if (st != JX_OK) {
+        fail("wait_any failed");
+        return;
+      }
+      double lat = 0.0;
+      if (jx_server_wait(s, tk, -1.0, obs.data(), rew.data(), dn.data(), &lat) != JX_OK) {
+        fail("a request failed");
+        return;
+      }
+      got[id].emplace_back(tk, lat);
+      double prev = t_last.load();
+      const double t = now_s();
+      while (t > prev && !t_last.compare_exchange_weak(prev, t)) {
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int i = 0; i < n_collectors; ++i) th.emplace_back(collector, i);
+  for (int32_t k = 0; k < n && !failed; ++k) {
+    for (;;) {  // sleep through long gaps, spin through short ones
+      const double w = t0 + t_arrival_s[k] - now_s();
+      if (w <= 0) break;
+      if (w > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(w - 1e-4));
+    }
+    if (jx_server_submit(s, client[k], actions_host[k], &ticket_of[k]) != JX_OK) {
+      fail("submit failed: " + std::string(jx_last_error()));
+      break;
+    }
+    if (close_after && close_after[k]) jx_server_close(s, client[k]);
+  }
+  const double t_sub = now_s() - t0;
+  for (auto& t : th) t.join();
+  if (failed) return set_error(JX_EDEVICE, err);
+  std::map<uint64_t, double> lat_of;
+  for (auto& v : got)
+    for (auto& p : v) lat_of[p.first] = p.second;
+  for (int32_t k = 0; k < n; ++k) {
+    auto it = lat_of.find(ticket_of[k]);
+    latency_s[k] = it == lat_of.end() ? -1.0 : it->second;
+  }
+  if (submitted_s) *submitted_s = t_sub;
+  if (wall_s) *wall_s = t_last.load() - t0;
   return JX_OK;
 }
 

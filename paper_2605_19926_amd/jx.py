@@ -112,6 +112,8 @@ _SIGS = {
     "jx_server_close": (_i32, [_vp, _i32]),
     "jx_server_wait_any": (_i32, [_vp, ctypes.c_double, ctypes.POINTER(_u64), ctypes.POINTER(_i32)]),
     "jx_server_get_stats": (_i32, [_vp, ctypes.POINTER(jx_server_stats)]),
+    "jx_server_replay": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, ctypes.c_double, _vp,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
 }
 
 _lib = None
@@ -456,6 +458,29 @@ class Server:
             return None
         check(rc)
         return cid.value, tk.value
+
+    def replay(self, t_arrival, clients, actions, close_after=None, n_collectors: int = 4,
+               timeout: float = 600.0):
+        """Native load generator (jx_server_replay): submits request k at
+        t_arrival[k] s for clients[k] with actions[k] (uint8 array of that
+        client's size), closing the client after it when close_after[k].
+        Returns (latency_s per request, submit seconds, wall seconds)."""
+        n = len(t_arrival)
+        t = np.ascontiguousarray(t_arrival, np.float64)
+        c = np.ascontiguousarray(clients, np.int32)
+        acts = [np.ascontiguousarray(a, np.uint8) for a in actions]
+        for k, a in enumerate(acts):
+            if a.size != self.sizes[int(c[k])][0]:
+                raise JxError(JX_EINVAL, f"request {k}: {a.size} actions for a client of "
+                                         f"{self.sizes[int(c[k])][0]} envs")
+        ptrs = np.array([a.ctypes.data for a in acts], np.uint64)
+        ca = None if close_after is None else np.ascontiguousarray(close_after, np.uint8)
+        lat = np.zeros(n, np.float64)
+        sub, wall = ctypes.c_double(), ctypes.c_double()
+        check(lib().jx_server_replay(self.h, n, t.ctypes.data, c.ctypes.data, ptrs.ctypes.data,
+                                     None if ca is None else ca.ctypes.data, n_collectors, timeout,
+                                     lat.ctypes.data, ctypes.byref(sub), ctypes.byref(wall)))
+        return lat, sub.value, wall.value
 
     def close_client(self, client: int):
         check(lib().jx_server_close(self.h, client))

@@ -95,6 +95,7 @@ def test_null_arguments_are_errors(jx):
     assert L.jx_reset(None, 1, None, None, 1, None, None) == jx.JX_EINVAL
     assert L.jx_make_layout(1, None, None) == jx.JX_EINVAL
     assert L.jx_server_submit(None, 0, None, None) == jx.JX_EINVAL
+    assert L.jx_server_replay(None, 1, None, None, None, None, 1, 0.0, None, None, None) == jx.JX_EINVAL
     assert L.jx_num_envs(None) == -1
     assert L.jx_obs_bytes(None) == -1
 

@@ -385,34 +385,71 @@ def test_serving_completion_queue():
             assert np.array_equal(a, b)
 
 
+def test_serving_native_replay():
+    """The native load generator: a dense trace (240 requests over 12 clients at
+    20,000 req/s) completes with every latency recorded, and every client's
+    requests ran in order: one more request per client afterwards returns the
+    same results as a server fed the same requests one by one."""
+    from paper_2605_19926_amd import jx
+    cfgs = [W.env_cfg(side=8 + 4 * (k % 3), obs_h=32 + 32 * (k % 2), obs_w=32 + 32 * (k % 2))
+            for k in range(12)]
+    sizes = [1 + 37 * k for k in range(12)]
+    rng = np.random.default_rng(3)
+    order = rng.integers(0, 12, size=240)
+    acts = [rng.integers(0, 6, size=sizes[c], dtype=np.uint8) for c in order]
+    finals = [rng.integers(0, 6, size=sizes[c], dtype=np.uint8) for c in range(12)]
+    results = []
+    for native in (True, False):
+        srv = jx.Server(hbm_budget=1 << 30, n_streams=4)
+        cids = [srv.open(W.seeds(200 + k, sizes[k]), cfgs[k])[0] for k in range(12)]
+        if native:
+            lat, sub, wall = srv.replay(np.arange(240) / 20000.0, [cids[c] for c in order], acts,
+                                        n_collectors=3, timeout=120.0)
+            assert (lat > 0).all() and wall > 0 and sub > 0
+            assert srv.stats()["requests"] == 240
+        else:
+            for c, a in zip(order, acts):
+                srv.wait(cids[c], srv.submit(cids[c], a))
+        results.append([srv.wait(cids[k], srv.submit(cids[k], finals[k]))[:3] for k in range(12)])
+        srv.close()
+    for k in range(12):
+        for a, b in zip(results[0][k], results[1][k]):
+            assert np.array_equal(a, b), f"client {k}"
+
+
 def test_serving_admission_by_budget():
+    """The HBM budget covers the admitted clients' state and maps: a client that
+    does not fit next to the resident ones waits for admission in FIFO order."""
     from paper_2605_19926_amd import jx
     cfg = W.env_cfg(side=32, obs_h=84, obs_w=84)
-    srv = jx.Server(hbm_budget=64 << 20, n_streams=2)
+    big_cfg = W.env_cfg(side=32, obs_h=16, obs_w=16)
+    small_n, big_n = 200, 6000
+    resident = 6 * jx.workspace_bytes(small_n, [cfg])
+    big_bytes = jx.workspace_bytes(big_n, [big_cfg])
+    srv = jx.Server(hbm_budget=resident + big_bytes - 4096, n_streams=2)
     ids = []
     admitted = []
     for k in range(6):
-        cid, ok = srv.open(W.seeds(70 + k, 200), cfg)   # ~4.5 MB each
+        cid, ok = srv.open(W.seeds(70 + k, small_n), cfg)
         ids.append(cid)
         admitted.append(ok)
     assert all(admitted)
-    big = W.seeds(80, 2000)                              # ~45 MB: must wait
-    cid, ok = srv.open(big, cfg)
+    cid, ok = srv.open(W.seeds(80, big_n), big_cfg)      # fits the budget alone, not beside them
     assert not ok
-    tk = srv.submit(cid, np.zeros(2000, np.uint8))
+    tk = srv.submit(cid, np.zeros(big_n, np.uint8))
     assert srv.wait(cid, tk, timeout=0.2) is None        # still queued for admission
     # closing a queued client keeps its queued request: it is admitted, runs it,
     # and the result stays collectable after the close
     srv.close_client(cid)
     # a queued client with nothing to run leaves the admission queue at once
-    idle, ok = srv.open(W.seeds(81, 2000), cfg)
+    idle, ok = srv.open(W.seeds(81, big_n), big_cfg)
     assert not ok
     srv.close_client(idle)
     for c in ids:
         srv.close_client(c)
     res = srv.wait(cid, tk, timeout=60.0)
-    assert res is not None and res[1].shape == (2000,)
-    assert res[0].shape == (2000, 84 * 84 * 3)
+    assert res is not None and res[1].shape == (big_n,)
+    assert res[0].shape == (big_n, 16 * 16 * 3)
     st = srv.stats()
     assert st["admission_waits"] >= 2
     assert st["clients_pending"] == 0
