@@ -436,7 +436,45 @@ def main() -> int:
                 "frame_bytes": fb // n, "obs_gbs": fb * Kb / bs / 1e9,
                 "frac_of_hbm_peak": fb * Kb / bs / 1e9 / HBM_PEAK_GBS}
 
-    shaded = ascii_maps = buffers = None
+    def keydoor_rate():
+        """The key-door workload (8192 envs, 32x32 loop-free mazes with door,
+        key, goal and decor sprites, 84x84 frames) in fused 128-step rollouts
+        into its own 128-slot ring, with the headline's launch mapping."""
+        kwl = W.KEYDOOR
+        kn = kwl["n_envs"]
+        kenv = jx.Env(W.seeds(kwl["number"], kn), kwl["cfg"])
+        kenv.reset()
+        kenv.set_launch(**launch)
+        kob = kenv.obs_bytes
+        T = 128
+        dev = kenv.dev
+        kacts = torch.from_numpy(W.actions(kwl["number"], T, kn, kwl["cfg"]["n_actions"])).to(dev)
+        kobs = torch.empty(T * kob, dtype=torch.uint8, device=dev)
+        krew = torch.empty(T * kn, dtype=torch.float32, device=dev)
+        kdone = torch.empty(T * kn, dtype=torch.uint8, device=dev)
+        launches = 4
+
+        def krun(count):
+            for _ in range(count):
+                kenv.rollout(kacts, kobs, krew, kdone, T, obs_stride=kob, graph=False, fused=True)
+        krun(1)
+        torch.cuda.synchronize()
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        krun(launches)
+        k1.record(stream)
+        torch.cuda.synchronize()
+        ks = k0.elapsed_time(k1) / 1e3
+        kenv.close()
+        del kobs
+        r = kn * T * launches / ks
+        progress(f"key-door workload: {r:.4g} env-steps/s")
+        return {"workload": kwl["name"], "steps": T * launches, "env_steps_per_s": r,
+                "ms_per_step": ks / (T * launches) * 1e3, "frame_bytes": kob // kn,
+                "obs_gbs": kob * T * launches / ks / 1e9,
+                "frac_of_hbm_peak": kob * T * launches / ks / 1e9 / HBM_PEAK_GBS}
+
+    shaded = ascii_maps = buffers = keydoor = None
     if args.form == "fused" and slots > 1:
         # distance-shaded walls (render option), same workload
         shaded = dict(shade_levels=8, shade_dist=12.0,
@@ -448,6 +486,7 @@ def main() -> int:
         # frames written straight into a learner's rollout buffer (with the
         # previous actions): NCHW float32 and u8, NHWC bfloat16
         buffers = [buffer_rate(1, 2), buffer_rate(0, 1), buffer_rate(1, 0)]
+        keydoor = keydoor_rate()
     S = env.get_state()
     line = {
         "metric": "rendered env-steps/s @4096 envs 64x64 RGB; served p50/p99 step latency vs plain",
@@ -481,6 +520,7 @@ def main() -> int:
         "distance_shading": shaded,
         "ascii_maps": ascii_maps,
         "training_buffer": buffers,
+        "keydoor_workload": keydoor,
         "obs_write_gbs": ab["obs"] * n * K / sec / 1e9,
         "episodes_completed": int(S["episode"].astype(np.int64).sum()),
         "wall_s": wall,
