@@ -651,7 +651,7 @@ int32_t orc_cast(const uint8_t* grid, int32_t N, int32_t door, int32_t door_open
   return o.hit;
 }
 
-/* Palette (the paper forgoes visual assets; these values are this build's). */
+/* Palette (the paper forgoes visual assets: the values are a convention, which the HIP path repeats independently). */
 static const uint8_t kPal[8][3] = {{180, 40, 40},  {40, 160, 40}, {40, 60, 180},  {190, 170, 40},
                                    {150, 40, 170}, {40, 160, 170}, {200, 110, 30}, {150, 150, 150}};
 static const uint8_t kCeil[3] = {50, 50, 60};

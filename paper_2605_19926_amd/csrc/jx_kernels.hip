@@ -30,7 +30,7 @@ namespace {
 
 constexpr uint32_t rgb(uint32_t r, uint32_t g, uint32_t b) { return r | (g << 8) | (b << 16); }
 
-// Colours of this build (the paper draws flat colours without assets).  The
+// Colours of this library (the paper draws flat colours without assets).  The
 // table is copied into each workgroup's LDS at kernel start: an indexed lookup
 // in LDS costs no global load, and a global load inside a step loop would
 // wait for every frame store the wave has in flight.
