@@ -101,7 +101,7 @@ def _oracle_chunk(args):
     return done
 
 
-def cpu_baseline(wl: dict, envs_per_worker: int = 64, steps: int = 1000) -> dict:
+def cpu_baseline(wl: dict, envs_per_worker: int = 64, steps: int = 3000) -> dict:
     """The oracle as it stands, on the host cores: one pinned core, then every
     core of this process's affinity set."""
     import oracle
