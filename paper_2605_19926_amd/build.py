@@ -17,6 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libjx.so")
+DEMO = os.path.join(PKG, "jx_demo")  # a C++ caller of the C-ABI (no Python)
 ARCH = os.environ.get("JX_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -53,8 +54,16 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    # the C++ demo links the library found next to it
+    tmp = DEMO + ".tmp"
+    cmd = [HIPCC, "-O2", "-std=c++17", f"-I{INCLUDE}"] + HOST_FLAGS + [os.path.join(CSRC, "jx_demo.cpp"),
+           "-x", "none", "-o", tmp, f"-L{PKG}", "-ljx", "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"demo build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, DEMO)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", DEMO)
     return OUT
 
 
