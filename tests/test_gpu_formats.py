@@ -52,6 +52,10 @@ CASES = [
                                obs_h=84, obs_w=84, episode_cap=64), 48),
     ("ascii-32x48", W.env_cfg(side=10, ascii_map=W.MAP10, goal_sprite=1, n_actions=4,
                               episode_cap=128, obs_h=32, obs_w=48), 16),
+    # the largest map and frame, and the smallest frame
+    ("max-64side-128px", W.env_cfg(side=64, loop_frac=0.1, key_door=1, goal_sprite=1, max_decor=2,
+                                   obs_h=128, obs_w=128, episode_cap=64), 8),
+    ("min-2x4px", W.env_cfg(side=5, goal_sprite=1, obs_h=2, obs_w=4, episode_cap=16), 8),
 ]
 
 
