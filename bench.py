@@ -147,7 +147,8 @@ def cpu_baseline(wl: dict, envs_per_worker: int = 64, steps: int = 3000) -> dict
 def batch_form(jx, torch, launches: list[dict], rollouts: int = 2) -> dict:
     """Mixed-shape batch (16384 envs: map side {8,16,32,64}, frames {32,64,128}
     square, key-door on half) stepped by 128-step hipGraph rollouts; env-steps/s
-    per launch mapping."""
+    per launch mapping, the given ones and the one the library's autotuner picks
+    (every candidate checked bit-identical to the default mapping)."""
     n, T = W.BATCH["n_envs"], W.BATCH["rollout"]
     cfgs, idx = W.batch_cfgs(n)
     env = jx.Env(W.seeds(W.BATCH["number"], n), cfgs, idx)
@@ -159,7 +160,10 @@ def batch_form(jx, torch, launches: list[dict], rollouts: int = 2) -> dict:
     acts = torch.from_numpy(W.actions(W.BATCH["number"], T, n, 6)).to(env.dev)
     out = {"workload": W.BATCH["name"], "n_envs": n, "rollout": T,
            "obs_bytes_per_step": ob, "results": []}
-    for launch in launches:
+    for launch in list(launches) + ["autotune"]:
+        tuned = launch == "autotune"
+        if tuned:
+            launch = env.autotune(acts, 16, obs[:ob])
         launch = dict(launch)
         fused = launch.pop("fused", False)
         env.set_launch(**launch)
@@ -174,6 +178,7 @@ def batch_form(jx, torch, launches: list[dict], rollouts: int = 2) -> dict:
         sec = e0.elapsed_time(e1) / 1e3
         steps = rollouts * T
         out["results"].append({"launch": launch, "rollout": "fused" if fused else "graph",
+                               "autotuned": tuned,
                                "env_steps_per_s": n * steps / sec,
                                "ms_per_step": sec / steps * 1e3,
                                "obs_gbs": ob * steps / sec / 1e9})
