@@ -323,8 +323,9 @@ jx_status jx_server_get_stats(jx_server* srv, jx_server_stats* out);
  * buffers of their own.  latency_s[k] receives request k's submit-to-ready
  * latency; submitted_s (nullable) the time the submits took; wall_s (nullable)
  * the time until the last result was collected.  Every client of the trace must
- * be open (admitted or queued).  Returns JX_EDEVICE if a request fails or the
- * replay exceeds timeout_s (> 0). */
+ * be open (admitted or queued), and no other requests may be submitted to srv
+ * while the replay runs.  Returns JX_EDEVICE if a request fails, a request not
+ * of the trace completes, or the replay exceeds timeout_s (> 0). */
 jx_status jx_server_replay(jx_server* srv, int32_t n, const double* t_arrival_s, const int32_t* client,
                            const uint8_t* const* actions_host, const uint8_t* close_after,
                            int32_t n_collectors, double timeout_s, double* latency_s,

@@ -855,6 +855,16 @@ jx_status jx_server_replay(jx_server* s, int32_t n, const double* t_arrival_s, c
         fail("wait_any failed");
         return;
       }
+      {
+        // the buffers are sized for the trace's clients: a request of another
+        // caller (which the replay must not run beside) would not fit
+        std::lock_guard<std::mutex> g(s->mu);
+        auto it = s->requests.find(tk);
+        if (it == s->requests.end() || it->second->n > max_n || it->second->obs_bytes > max_obs) {
+          fail("replay: a request not of the trace completed during the replay");
+          return;
+        }
+      }
       double lat = 0.0;
       if (jx_server_wait(s, tk, -1.0, obs.data(), rew.data(), dn.data(), &lat) != JX_OK) {
         fail("a request failed");
