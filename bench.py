@@ -544,8 +544,12 @@ def main() -> int:
             "workload": W.SERVE["name"],
             "runs": [serve_form(jx, nr, jx.JX_SERVE_COALESCE),
                      serve_form(jx, nr, jx.JX_SERVE_PLAIN),
+                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, rate=4 * W.SERVE["rate"]),
+                     serve_form(jx, nr, jx.JX_SERVE_PLAIN, rate=4 * W.SERVE["rate"]),
                      serve_form(jx, nr, jx.JX_SERVE_COALESCE, rate=8 * W.SERVE["rate"]),
                      serve_form(jx, nr, jx.JX_SERVE_PLAIN, rate=8 * W.SERVE["rate"]),
+                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, rate=16 * W.SERVE["rate"]),
+                     serve_form(jx, nr, jx.JX_SERVE_PLAIN, rate=16 * W.SERVE["rate"]),
                      serve_form(jx, nr, jx.JX_SERVE_COALESCE, budget=24 << 20)]}
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle on the host cores)")
