@@ -259,8 +259,9 @@ def main() -> int:
                          "HBM traffic counters, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); envs shard "
-              "independently across GPUs, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the envs are "
+              "independent, so a multi-GPU job would give each GPU its own env range, "
+              "workspace and stream, and exchange nothing per step", file=sys.stderr)
         return 2
 
     import torch

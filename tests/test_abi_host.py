@@ -137,3 +137,14 @@ def test_host_ascii_rejects(jx, text, kw):
     cfg = W.env_cfg(ascii_map=text, **kw)
     with pytest.raises(jx.JxError):
         jx.make_layout(0, cfg)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: asking for more exits with a message, before
+    touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
