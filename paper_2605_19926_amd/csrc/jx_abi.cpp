@@ -804,10 +804,15 @@ extern "C" jx_status jx_autotune(jx_ctx* c, const uint8_t* actions, int32_t iter
   }
   float* rew = (float*)io_buf;
   uint8_t* dn = io_buf + (size_t)iters * n * 4;
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
-  HIPCHK(hipMemcpyAsync(snap, c->ws, total, hipMemcpyDeviceToDevice, c->stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipMemcpyAsync(snap, c->ws, total, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(snap);
+    hipFree(io_buf);
+    return set_error(JX_EDEVICE, "autotune set-up failed");
+  }
 
   std::vector<LaunchCfg> cands;
   for (int w : {1, 2, 4, 8})
@@ -828,8 +833,11 @@ extern "C" jx_status jx_autotune(jx_ctx* c, const uint8_t* actions, int32_t iter
     c->launch = cands[k];
     float ms_min = 1e30f;
     for (int rep = 0; rep < 2 && result == JX_OK; ++rep) {
-      hipMemcpyAsync(c->ws, snap, total, hipMemcpyDeviceToDevice, c->stream);
-      hipEventRecord(e0, c->stream);
+      if (hipMemcpyAsync(c->ws, snap, total, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+          hipEventRecord(e0, c->stream) != hipSuccess) {
+        result = set_error(JX_EDEVICE, "autotune: state restore failed");
+        break;
+      }
       for (int t = 0; t < iters && result == JX_OK; ++t) {
         DevIo io{};
         io.act = actions + (int64_t)t * n;
@@ -840,19 +848,25 @@ extern "C" jx_status jx_autotune(jx_ctx* c, const uint8_t* actions, int32_t iter
         io.store_mode = c->launch.store_mode;
         result = launch_or_fail(c, io, c->stream);
       }
-      hipEventRecord(e1, c->stream);
-      if (hipStreamSynchronize(c->stream) != hipSuccess) result = set_error(JX_EDEVICE, "autotune run failed");
+      if (result != JX_OK) break;
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (hipEventRecord(e1, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        result = set_error(JX_EDEVICE, "autotune run failed");
+        break;
+      }
       ms_min = std::min(ms_min, ms);
     }
     if (result != JX_OK) break;
     std::vector<uint8_t>& o = (k == 0) ? ref_obs : cur_obs;
     std::vector<uint8_t>& s = (k == 0) ? ref_state : cur_state;
     std::vector<uint8_t>& i2 = (k == 0) ? ref_io : cur_io;
-    hipMemcpy(o.data(), obs_scratch, ob, hipMemcpyDeviceToHost);
-    hipMemcpy(s.data(), c->ws, total, hipMemcpyDeviceToHost);
-    hipMemcpy(i2.data(), io_buf, i2.size(), hipMemcpyDeviceToHost);
+    if (hipMemcpy(o.data(), obs_scratch, ob, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(s.data(), c->ws, total, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(i2.data(), io_buf, i2.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+      result = set_error(JX_EDEVICE, "autotune: result copy failed");
+      break;
+    }
     const bool same = (k == 0) || (o == ref_obs && s == ref_state && i2 == ref_io);
     if (!same) {
       result = set_error(JX_EDEVICE, "autotune: candidate mapping changed the results");
@@ -863,8 +877,10 @@ extern "C" jx_status jx_autotune(jx_ctx* c, const uint8_t* actions, int32_t iter
       best = cands[k];
     }
   }
-  hipMemcpyAsync(c->ws, snap, total, hipMemcpyDeviceToDevice, c->stream);
-  hipStreamSynchronize(c->stream);
+  // the caller's state comes back whatever happened above
+  if ((hipMemcpyAsync(c->ws, snap, total, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+       hipStreamSynchronize(c->stream) != hipSuccess) && result == JX_OK)
+    result = set_error(JX_EDEVICE, "autotune: state restore failed");
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipFree(snap);
