@@ -311,6 +311,13 @@ def test_serving_alone_equals_mix_equals_plain():
     env = U.env_of(cfg, seeds, obs=False)
     plain = _run(env, torch.from_numpy(acts).to(env.dev), T, "eager", torch)
     env.close()
+    # an ASCII-map client (keys, doors, candidates) in the same mix
+    acfg = W.ASCII_TINY["cfg"]
+    aseeds = W.seeds(7, 16)
+    aacts = W.actions(7, T, 16, acfg["n_actions"])
+    env = U.env_of(acfg, aseeds, obs=False)
+    aplain = _run(env, torch.from_numpy(aacts).to(env.dev), T, "eager", torch)
+    env.close()
     # served alone
     srv = jx.Server(hbm_budget=1 << 30, n_streams=4)
     cid, ok = srv.open(seeds, cfg)
@@ -328,11 +335,15 @@ def test_serving_alone_equals_mix_equals_plain():
         o, _ = srv.open(s2, c2)
         others.append((o, W.actions(60 + k, T, len(s2), 6)))
     results = {}
+    acid, _ = srv.open(aseeds, acfg)
 
     def client(o, a):
         results[o] = _serve_run(srv, o, a, want_obs=False)
 
-    th = [threading.Thread(target=client, args=oa) for oa in others]
+    def ascii_client():
+        results["ascii"] = _serve_run(srv, acid, aacts)
+
+    th = [threading.Thread(target=client, args=oa) for oa in others] + [threading.Thread(target=ascii_client)]
     for t_ in th:
         t_.start()
     mix = _serve_run(srv, cid, acts)
@@ -347,7 +358,13 @@ def test_serving_alone_equals_mix_equals_plain():
             assert np.array_equal(res[0], p_obs), f"step {t}: frames differ"
             assert np.array_equal(res[1], plain[1][t * n:(t + 1) * n])
             assert np.array_equal(res[2], plain[2][t * n:(t + 1) * n])
-    assert st["requests"] >= T * 7
+    ob2 = acfg["obs_h"] * acfg["obs_w"] * 3
+    for t in range(T):
+        res = results["ascii"][t]
+        assert np.array_equal(res[0], aplain[0][t * 16 * ob2:(t + 1) * 16 * ob2].reshape(16, ob2)), f"ascii step {t}"
+        assert np.array_equal(res[1], aplain[1][t * 16:(t + 1) * 16])
+        assert np.array_equal(res[2], aplain[2][t * 16:(t + 1) * 16])
+    assert st["requests"] >= T * 8
     assert st["launches"] < st["requests"]          # requests were coalesced
     assert all(len(v) == T for v in results.values())
 
