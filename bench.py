@@ -552,6 +552,14 @@ def main() -> int:
                      serve_form(jx, nr, jx.JX_SERVE_COALESCE, rate=16 * W.SERVE["rate"]),
                      serve_form(jx, nr, jx.JX_SERVE_PLAIN, rate=16 * W.SERVE["rate"]),
                      serve_form(jx, nr, jx.JX_SERVE_COALESCE, budget=24 << 20)]}
+        # the metric's second half: served step latency vs the plain per-request
+        # launch at the serving workload's own arrival rate
+        runs = line["serving_form"]["runs"]
+        line["served_latency"] = {"offered_req_per_s": runs[0]["offered_req_per_s"],
+                                  "coalesced_p50_ms": runs[0]["p50_ms"], "coalesced_p99_ms": runs[0]["p99_ms"],
+                                  "plain_p50_ms": runs[1]["p50_ms"], "plain_p99_ms": runs[1]["p99_ms"],
+                                  "coalesced_env_steps_per_s": runs[0]["env_steps_per_s"],
+                                  "plain_env_steps_per_s": runs[1]["env_steps_per_s"]}
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle on the host cores)")
         line["cpu_baseline"] = cpu_baseline(wl)
