@@ -131,14 +131,21 @@ def _trajectory(cfg, seeds, acts, mode):
     return out, offs, ob
 
 
-@pytest.mark.parametrize("layout,dtype", [(1, 2), (0, 1), (1, 0)])
-def test_format_is_the_byte_frame_converted_in_every_form(layout, dtype):
-    base = W.env_cfg(side=16, n_colors=8, loop_frac=0.1, goal_sprite=1, key_door=1, max_decor=1,
-                     n_actions=6, episode_cap=24, obs_h=64, obs_w=64)
+MAZE_KD = W.env_cfg(side=16, n_colors=8, loop_frac=0.1, goal_sprite=1, key_door=1, max_decor=1,
+                    n_actions=6, episode_cap=24, obs_h=64, obs_w=64)
+ASCII_64 = W.env_cfg(side=10, ascii_map=W.MAP10, goal_sprite=1, n_actions=4, episode_cap=24,
+                     obs_h=64, obs_w=64)
+
+
+@pytest.mark.parametrize("base,layout,dtype", [(MAZE_KD, 1, 2), (MAZE_KD, 0, 1), (MAZE_KD, 1, 0),
+                                               (ASCII_64, 1, 2), (ASCII_64, 0, 1)],
+                         ids=["maze-nchw-f32", "maze-nhwc-bf16", "maze-nchw-u8", "ascii-nchw-f32",
+                              "ascii-nhwc-bf16"])
+def test_format_is_the_byte_frame_converted_in_every_form(base, layout, dtype):
     cfg = fmt_cfg(base, layout, dtype)
     n, T = 96, 40
     seeds = W.seeds(33, n)
-    acts = W.actions(34, T, n, 7)                       # 6 is out of range
+    acts = W.actions(34, T, n, base["n_actions"] + 1)   # the last code is out of range
     (ref_obs, ref_rew, ref_done, ref_prev, _), offs, ob = _trajectory(base, seeds, acts, "eager")
     tab32 = np.array([orc.norm_f32(b) for b in range(256)], np.float32).view(np.uint32)
     tab16 = np.array([orc.norm_bf16(b) for b in range(256)], np.uint16)
