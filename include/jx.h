@@ -266,10 +266,11 @@ jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_by
                            int32_t n_streams, int32_t mode, int32_t max_batch_envs);
 void jx_server_destroy(jx_server* srv);
 
-/* Opens a client of n_envs envs (one configuration for all).  Returns JX_OK
- * when admitted, JX_EBUSY when queued for admission (the id is valid either
- * way; requests submitted meanwhile wait), JX_ENOMEM when the client alone
- * exceeds the budget. */
+/* Opens a client of n_envs envs (one configuration for all; the default frame
+ * format only).  Returns JX_OK when admitted, JX_EBUSY when queued for
+ * admission (the id is valid either way; requests submitted meanwhile wait),
+ * JX_ENOMEM when the client's state alone exceeds the budget or one step of it
+ * does not fit the launch staging, JX_EINVAL for a bad configuration. */
 jx_status jx_server_open(jx_server* srv, int32_t n_envs, const uint64_t* seeds_host,
                          const jx_env_cfg* cfg, int32_t* client);
 
