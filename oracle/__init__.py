@@ -143,6 +143,9 @@ def lib():
         L.orc_render.argtypes = [u8p, ctypes.POINTER(OrcCfg), ctypes.POINTER(OrcState), u8p,
                                  i32p, i32p, f64p, i32p, i32p, i32p, f64p]
         L.orc_render.restype = ctypes.c_int32
+        L.orc_render_ex.argtypes = [u8p, ctypes.POINTER(OrcCfg), ctypes.POINTER(OrcState),
+                                    ctypes.c_int32, u8p, i32p, i32p, f64p, i32p, i32p, i32p, f64p, u8p]
+        L.orc_render_ex.restype = ctypes.c_int32
         L.orc_cast.argtypes = [u8p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, i32p, f64p, i32p]
@@ -150,7 +153,7 @@ def lib():
         L.orc_ascii.argtypes = [ctypes.c_char_p, ctypes.c_int32, u8p, ctypes.POINTER(ctypes.c_int32)]
         L.orc_ascii.restype = ctypes.c_int32
         L.orc_rollout.argtypes = [ctypes.POINTER(OrcCfg), ctypes.c_int32, u64p, ctypes.c_int32,
-                                  u8p, u8p]
+                                  u8p, u8p, ctypes.POINTER(ctypes.c_int64)]
         L.orc_rollout.restype = ctypes.c_int64
         L.orc_norm_f32.argtypes = [ctypes.c_int32]
         L.orc_norm_f32.restype = ctypes.c_float
@@ -245,20 +248,23 @@ def step(grid: np.ndarray, cfg: OrcCfg, seed: int, state: OrcState, action: int,
     return out, r.value, d.value, ev.value, sf.value
 
 
-def render(grid: np.ndarray, cfg: OrcCfg, state: OrcState):
-    """Returns (obs[H,W,3] uint8, per-column dict: hit, side, t, flags, alt_hit, alt_side, alt_t)."""
+def render(grid: np.ndarray, cfg: OrcCfg, state: OrcState, branch: int = 0):
+    """Returns (obs[H,W,3] uint8, per-column dict: hit, side, t, flags, alt_hit,
+    alt_side, alt_t, and tie[H,W]: 1 where the pixel is decided inside a
+    window).  branch 1 renders every flagged DDA tie's other side."""
     g = np.ascontiguousarray(grid, np.uint8)
     H, W = cfg.obs_h, cfg.obs_w
     obs = np.zeros((H, W, 3), np.uint8)
     cols = {"hit": np.zeros(W, np.int32), "side": np.zeros(W, np.int32),
             "t": np.zeros(W, np.float64), "flags": np.zeros(W, np.int32),
             "alt_hit": np.zeros(W, np.int32), "alt_side": np.zeros(W, np.int32),
-            "alt_t": np.zeros(W, np.float64)}
-    rc = lib().orc_render(_p(g, ctypes.c_uint8), ctypes.byref(cfg), ctypes.byref(state),
-                          _p(obs, ctypes.c_uint8), _p(cols["hit"], ctypes.c_int32),
-                          _p(cols["side"], ctypes.c_int32), _p(cols["t"], ctypes.c_double),
-                          _p(cols["flags"], ctypes.c_int32), _p(cols["alt_hit"], ctypes.c_int32),
-                          _p(cols["alt_side"], ctypes.c_int32), _p(cols["alt_t"], ctypes.c_double))
+            "alt_t": np.zeros(W, np.float64), "tie": np.zeros((H, W), np.uint8)}
+    rc = lib().orc_render_ex(_p(g, ctypes.c_uint8), ctypes.byref(cfg), ctypes.byref(state),
+                             int(branch), _p(obs, ctypes.c_uint8), _p(cols["hit"], ctypes.c_int32),
+                             _p(cols["side"], ctypes.c_int32), _p(cols["t"], ctypes.c_double),
+                             _p(cols["flags"], ctypes.c_int32), _p(cols["alt_hit"], ctypes.c_int32),
+                             _p(cols["alt_side"], ctypes.c_int32), _p(cols["alt_t"], ctypes.c_double),
+                             _p(cols["tie"], ctypes.c_uint8))
     if rc != 0:
         raise ValueError("render failed")
     return obs, cols
@@ -275,17 +281,25 @@ def cast(grid: np.ndarray, door: int, door_open: int, x: float, y: float, rx: fl
     return hit, side.value, t.value, fl.value
 
 
-def rollout(cfg: OrcCfg, seeds: np.ndarray, actions: np.ndarray, want_obs: bool = False):
-    """Steps len(seeds) envs through actions[T, n]; returns (env_steps, last_obs or None)."""
+def rollout(cfg: OrcCfg, seeds: np.ndarray, actions: np.ndarray, want_obs: bool = False,
+            counts: bool = False):
+    """Steps len(seeds) envs through actions[T, n]; returns (env_steps, last_obs
+    or None), and with counts=True a third item: {columns, flagged, f1,
+    steps_flagged} over every rendered frame."""
     seeds = np.ascontiguousarray(seeds, np.uint64)
     actions = np.ascontiguousarray(actions, np.uint8)
     n = seeds.shape[0]
     T = actions.shape[0]
     assert actions.shape == (T, n)
     last = np.zeros((n, cfg.obs_h, cfg.obs_w, 3), np.uint8) if want_obs else None
+    cnt = np.zeros(4, np.int64)
     done = lib().orc_rollout(ctypes.byref(cfg), n, _p(seeds, ctypes.c_uint64), T,
                              _p(actions, ctypes.c_uint8),
-                             _p(last, ctypes.c_uint8) if want_obs else None)
+                             _p(last, ctypes.c_uint8) if want_obs else None,
+                             _p(cnt, ctypes.c_int64) if counts else None)
+    if counts:
+        return done, last, {"columns": int(cnt[0]), "flagged": int(cnt[1]), "f1": int(cnt[2]),
+                            "steps_flagged": int(cnt[3])}
     return done, last
 
 

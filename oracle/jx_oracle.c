@@ -685,10 +685,26 @@ static const uint8_t kAKeyCol[3][3] = {{255, 40, 40}, {40, 110, 255}, {255, 200,
 /* row r when |r+0.5-H/2| < half-height.  Painted far to near (descending    */
 /* tY; equal tY in ascending index, so the later index wins).                */
 /* ------------------------------------------------------------------------ */
-int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st, uint8_t* obs,
-                   int32_t* hit, int32_t* side, double* tstar, int32_t* cflags, int32_t* alt_hit,
-                   int32_t* alt_side, double* alt_t) {
-  if (!grid || !cfg || !st || !obs) return -1;
+/* Marks the rows at distance k from the horizon (row H/2-1-k above, H/2+k
+ * below) of column col in the tie mask. */
+static void tie_pair(uint8_t* tie, int32_t H, int32_t W, int32_t col, int32_t k) {
+  if (!tie || k < 0 || k >= H / 2) return;
+  tie[(size_t)(H / 2 - 1 - k) * W + col] = 1;
+  tie[(size_t)(H / 2 + k) * W + col] = 1;
+}
+
+/* Marks every row r of column col with |r + 0.5 - H/2| < extent (the rows a
+ * wall span or a billboard of that half-height covers). */
+static void tie_band(uint8_t* tie, int32_t H, int32_t W, int32_t col, double extent) {
+  if (!tie) return;
+  for (int32_t r = 0; r < H; ++r)
+    if (fabs(r + 0.5 - H / 2.0) < extent) tie[(size_t)r * W + col] = 1;
+}
+
+int32_t orc_render_ex(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st, int32_t branch,
+                      uint8_t* obs, int32_t* hit, int32_t* side, double* tstar, int32_t* cflags,
+                      int32_t* alt_hit, int32_t* alt_side, double* alt_t, uint8_t* tie) {
+  if (!grid || !cfg || !st || !obs || (branch != 0 && branch != 1)) return -1;
   const int32_t N = cfg->side, H = cfg->obs_h, W = cfg->obs_w;
   const int32_t K = cfg->n_colors;
   if (W <= 0 || H <= 0 || K < 1 || K > 8) return -1;
@@ -697,6 +713,7 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
   const double dirx = c, diry = s, rgtx = -s, rgty = c;
   const int32_t door = st->door, dopen = st->door_open;
   const double half = H / 2.0;
+  if (tie) memset(tie, 0, (size_t)H * W);
 
   double* tcol = (double*)malloc(sizeof(double) * (size_t)W);
   int32_t* fl = (int32_t*)calloc((size_t)W, sizeof(int32_t));
@@ -705,54 +722,60 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
     double camX = (2.0 * col + 1.0 - W) / (double)W;
     double rx = dirx + camX * tanH * rgtx;
     double ry = diry + camX * tanH * rgty;
-    cast_out o;
+    cast_out o, a;
     cast_walk(grid, N, door, dopen, st->doors_open, st->x, st->y, rx, ry, -1, &o);
     if (o.n_ties > 0) fl[col] |= ORC_CF_DDA;
     if (o.n_ties > 1) fl[col] |= ORC_CF_MULTI;
-    if (alt_hit || alt_side || alt_t) {
-      int32_t ah = -1, as = 0;
-      double at = 0.0;
-      if (o.n_ties > 0) {
-        cast_out a;
-        cast_walk(grid, N, door, dopen, st->doors_open, st->x, st->y, rx, ry, o.first_tie, &a);
-        ah = a.hit;
-        as = a.side;
-        at = a.t;
-      }
-      if (alt_hit) alt_hit[col] = ah;
-      if (alt_side) alt_side[col] = as;
-      if (alt_t) alt_t[col] = at;
-    }
-    tcol[col] = o.t;
-    if (hit) hit[col] = o.hit;
-    if (side) side[col] = o.side;
-    if (tstar) tstar[col] = o.t;
+    a.hit = -1;
+    a.side = 0;
+    a.t = 0.0;
+    if (o.n_ties > 0)
+      cast_walk(grid, N, door, dopen, st->doors_open, st->x, st->y, rx, ry, o.first_tie, &a);
+    if (alt_hit) alt_hit[col] = a.hit;
+    if (alt_side) alt_side[col] = a.side;
+    if (alt_t) alt_t[col] = a.t;
+    /* the walk this frame shows: branch 1 takes the other side of the first
+     * flagged tie (the second valid result of the column, Sec. 2.1 DDA) */
+    const cast_out* u = (branch == 1 && o.n_ties > 0) ? &a : &o;
+    tcol[col] = u->t;
+    if (hit) hit[col] = u->hit;
+    if (side) side[col] = u->side;
+    if (tstar) tstar[col] = u->t;
 
     uint8_t wc[3];
-    const uint8_t hv = o.hit >= 0 ? grid[o.hit] : 1;
+    const uint8_t hv = u->hit >= 0 ? grid[u->hit] : 1;
     const uint8_t* base;
-    if (o.hit == door && !dopen) base = kDoor;
+    if (u->hit == door && !dopen) base = kDoor;
     else if (hv & ORC_TILE_DOOR) base = kDoorCol[(hv >> 4) & 7];
     else if ((hv & 0x0F) >= 2) base = kWall9[(hv & 0x0F) - 2];
-    else base = kPal[(o.hit < 0 ? 0 : o.hit) % K];
-    for (int32_t ch = 0; ch < 3; ++ch) wc[ch] = o.side ? (uint8_t)(base[ch] >> 1) : base[ch];
+    else base = kPal[(u->hit < 0 ? 0 : u->hit) % K];
+    for (int32_t ch = 0; ch < 3; ++ch) wc[ch] = u->side ? (uint8_t)(base[ch] >> 1) : base[ch];
+    double hh = H / (2.0 * u->t);
     if (cfg->shade_levels > 0) {
       /* Distance shading (the ray-casting section lets the wall colour depend
        * on the hit distance; this is the library's reading): S levels over
        * [0, D), level l = floor(t* S / D) capped at S - 1, and each channel of
        * the wall colour keeps the fraction (S - l) / S, rounded down. */
       const int32_t S = cfg->shade_levels;
-      const double q = o.t * (double)S / cfg->shade_dist;
+      const double q = u->t * (double)S / cfg->shade_dist;
       int32_t lv = (int32_t)floor(q);
       if (lv > S - 1) lv = S - 1;
       for (int32_t ch = 0; ch < 3; ++ch) wc[ch] = (uint8_t)((wc[ch] * (S - lv)) / S);
-      /* F4: the level boundaries are the integers 1..S-1 of q */
+      /* F4: the level boundaries are the integers 1..S-1 of q; the level
+       * decides the colour of every wall row */
       for (int32_t k = 1; k < S; ++k)
-        if (fabs(q - k) <= 1e-5 * q) fl[col] |= ORC_CF_SHADE;
+        if (fabs(q - k) <= 1e-5 * q) {
+          fl[col] |= ORC_CF_SHADE;
+          tie_band(tie, H, W, col, hh);
+        }
     }
-    double hh = H / (2.0 * o.t);
+    /* F2: a pixel centre within the window of the span's edge decides that
+     * row pair */
     for (int32_t k = 0; k < H / 2; ++k)
-      if (fabs(hh - (k + 0.5)) <= 1e-5 * hh) fl[col] |= ORC_CF_SPAN;
+      if (fabs(hh - (k + 0.5)) <= 1e-5 * hh) {
+        fl[col] |= ORC_CF_SPAN;
+        tie_pair(tie, H, W, col, k);
+      }
     for (int32_t r = 0; r < H; ++r) {
       const uint8_t* px;
       if (fabs(r + 0.5 - half) < hh) px = wc;
@@ -820,7 +843,10 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
       }
     }
   }
-  /* F3: sprite comparisons inside their windows */
+  /* F3: sprite comparisons inside their windows.  A tied horizontal edge,
+   * z-test or near clip decides whether the billboard shows on the column at
+   * all (its rows are tied); a tied vertical edge decides one row pair; a tied
+   * depth between two billboards decides which of them shows on their rows. */
   for (int32_t j = 0; j < ns; ++j) {
     if (tY[j] <= 0.0) continue;
     double wn = 1e-5 * (1.0 + dn[j]);
@@ -833,15 +859,22 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
       double wz = 1e-5 * (1.0 + dn[j] + tcol[col]);
       double zt = tY[j] - tcol[col];
       int flag = near_clip || fabs(e) < wu || fabs(zt) <= wz;
+      if (flag) tie_band(tie, H, W, col, hs[j] * (1.0 + 1e-5));
       int covered = vis[j] && e < 0.0 && zt < 0.0;
       if (covered) {
         for (int32_t k = 0; k < H / 2; ++k)
-          if (fabs(hs[j] - (k + 0.5)) <= 1e-5 * hs[j]) flag = 1;
+          if (fabs(hs[j] - (k + 0.5)) <= 1e-5 * hs[j]) {
+            flag = 1;
+            tie_pair(tie, H, W, col, k);
+          }
         for (int32_t q = 0; q < ns; ++q) {
           if (q == j || tY[q] <= 0.05) continue;
           if (fabs(col + 0.5 - u[q]) - hw[q] >= 1e-5 * (1.0 + fabs(u[q]) + hw[q]) * (1.0 + dn[q] / tY[q]))
             continue;
-          if (fabs(tY[q] - tY[j]) <= 1e-5 * (1.0 + dn[j] + dn[q])) flag = 1;
+          if (fabs(tY[q] - tY[j]) <= 1e-5 * (1.0 + dn[j] + dn[q])) {
+            flag = 1;
+            tie_band(tie, H, W, col, hs[j] * (1.0 + 1e-5));
+          }
         }
       }
       if (flag) fl[col] |= ORC_CF_SPRITE;
@@ -854,14 +887,22 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
   return 0;
 }
 
+int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st, uint8_t* obs,
+                   int32_t* hit, int32_t* side, double* tstar, int32_t* cflags, int32_t* alt_hit,
+                   int32_t* alt_side, double* alt_t) {
+  return orc_render_ex(grid, cfg, st, 0, obs, hit, side, tstar, cflags, alt_hit, alt_side, alt_t, NULL);
+}
+
 int64_t orc_rollout(const orc_cfg* cfg, int32_t n_envs, const uint64_t* seeds, int32_t n_steps,
-                    const uint8_t* actions, uint8_t* last_obs) {
+                    const uint8_t* actions, uint8_t* last_obs, int64_t* counts) {
   if (!cfg || n_envs < 0 || !seeds || n_steps < 0 || !actions) return -1;
   const int32_t N = cfg->side;
   const size_t fb = (size_t)cfg->obs_h * cfg->obs_w * 3;
   uint8_t* grid = (uint8_t*)malloc((size_t)N * N);
   uint8_t* obs = (uint8_t*)malloc(fb);
+  int32_t* fl = (int32_t*)malloc(sizeof(int32_t) * (size_t)cfg->obs_w);
   int64_t done_steps = 0;
+  if (counts) counts[0] = counts[1] = counts[2] = counts[3] = 0;
   for (int32_t i = 0; i < n_envs; ++i) {
     int32_t keys3[3];
     if (cfg->ascii_map ? orc_ascii(cfg->ascii_map, N, grid, keys3) < 0
@@ -874,13 +915,23 @@ int64_t orc_rollout(const orc_cfg* cfg, int32_t n_envs, const uint64_t* seeds, i
       int32_t d, ev, sf;
       orc_step(grid, cfg, seeds[i], &st, actions[(size_t)t * n_envs + i], &nx, &r, &d, &ev, &sf);
       st = nx;
-      orc_render(grid, cfg, &st, obs, NULL, NULL, NULL, NULL, NULL, NULL, NULL);
+      orc_render(grid, cfg, &st, obs, NULL, NULL, NULL, counts ? fl : NULL, NULL, NULL, NULL);
+      if (counts) {
+        /* columns rendered, columns flagged, F1 columns, steps flagged */
+        counts[0] += cfg->obs_w;
+        for (int32_t c = 0; c < cfg->obs_w; ++c) {
+          counts[1] += fl[c] != 0;
+          counts[2] += (fl[c] & ORC_CF_DDA) != 0;
+        }
+        counts[3] += sf != 0;
+      }
       ++done_steps;
     }
     if (last_obs) memcpy(last_obs + (size_t)i * fb, obs, fb);
   }
   free(grid);
   free(obs);
+  free(fl);
   return done_steps;
 }
 

@@ -143,6 +143,24 @@ int32_t orc_render(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st,
                    uint8_t* obs, int32_t* hit, int32_t* side, double* tstar,
                    int32_t* cflags, int32_t* alt_hit, int32_t* alt_side, double* alt_t);
 
+/* The same render with the acceptance data of a frame whose decisions sit
+ * inside their windows (several results are then correct, Sec. 2.1 DDA):
+ *   branch 0: the frame of orc_render; branch 1: every column with a flagged
+ *     DDA tie takes the other side of its first tie (the column's second valid
+ *     result: hit, side and t* of that walk, sprites z-tested against that t*);
+ *     the per-column outputs then describe that walk (alt_* still the walk
+ *     not taken by branch 0).
+ *   tie (nullable) [H][W]: 1 on every pixel whose value is decided by a
+ *     comparison inside its window on this frame: the row pair of a tied span
+ *     edge (F2), every wall row of a column whose shading level is tied (F4),
+ *     every row of a billboard whose horizontal edge, z-test or near clip is
+ *     tied on that column, or whose depth ties another's, and the row pair of
+ *     its tied vertical edge (F3).  Every other pixel has one correct value.
+ * Returns 0, or -1 on bad arguments. */
+int32_t orc_render_ex(const uint8_t* grid, const orc_cfg* cfg, const orc_state* st, int32_t branch,
+                      uint8_t* obs, int32_t* hit, int32_t* side, double* tstar, int32_t* cflags,
+                      int32_t* alt_hit, int32_t* alt_side, double* alt_t, uint8_t* tie);
+
 /* Single-ray query used by the closed-form tests: casts from (x, y) along
  * (rx, ry) and reports the first blocking tile.  Returns the hit tile id. */
 int32_t orc_cast(const uint8_t* grid, int32_t N, int32_t door, int32_t door_open,
@@ -173,9 +191,12 @@ int32_t orc_prev_action(const orc_cfg* cfg, int32_t action, int32_t done);
 
 /* Runs `n_steps` steps of `n_envs` environments, each from episode 0, with
  * actions[t*n_envs+i], rendering every frame into a scratch buffer.  This is
- * the timed CPU baseline; returns the number of env-steps done. */
+ * the timed CPU baseline; returns the number of env-steps done.  counts
+ * (nullable) [4] receives the columns rendered, the columns flagged (any of
+ * F1-F4), the F1 columns and the steps flagged (S1-S3). */
 int64_t orc_rollout(const orc_cfg* cfg, int32_t n_envs, const uint64_t* seeds,
-                    int32_t n_steps, const uint8_t* actions, uint8_t* last_obs);
+                    int32_t n_steps, const uint8_t* actions, uint8_t* last_obs,
+                    int64_t* counts);
 
 #ifdef __cplusplus
 }
