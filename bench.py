@@ -97,51 +97,81 @@ def _oracle_chunk(args):
     cfg_d, seeds, acts = args
     import oracle
     c = oracle.make_cfg(cfg_d)
-    done, _ = oracle.rollout(c, seeds, acts)
-    return done
+    done, _, counts = oracle.rollout(c, seeds, acts, counts=True)
+    return done, counts
 
 
-def cpu_baseline(wl: dict, envs_per_worker: int = 64, steps: int = 3000) -> dict:
-    """The oracle as it stands, on the host cores: one pinned core, then every
-    core of this process's affinity set."""
-    import oracle
-    oracle.build()
-    cfg = wl["cfg"]
-    cores = sorted(os.sched_getaffinity(0))
-    n_workers = min(len(cores), 16)
-    seeds = W.seeds(wl["number"], envs_per_worker * n_workers)
-    acts = W.actions(wl["number"], steps, envs_per_worker * n_workers, cfg["n_actions"])
-    # one core
-    prev = os.sched_getaffinity(0)
-    os.sched_setaffinity(0, {cores[0]})
-    t0 = time.perf_counter()
-    one = _oracle_chunk((cfg, seeds[:envs_per_worker], np.ascontiguousarray(acts[:, :envs_per_worker])))
-    dt1 = time.perf_counter() - t0
-    os.sched_setaffinity(0, prev)
-    # all cores
-    chunks = [(cfg, seeds[k * envs_per_worker:(k + 1) * envs_per_worker],
-               np.ascontiguousarray(acts[:, k * envs_per_worker:(k + 1) * envs_per_worker]))
-              for k in range(n_workers)]
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(n_workers) as pool:
-        pool.map(_oracle_chunk, chunks[:1])          # start-up outside the timing
-        t0 = time.perf_counter()
-        tot = sum(pool.map(_oracle_chunk, chunks))
-        dtn = time.perf_counter() - t0
-    model = "unknown"
+def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
                 if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
+    return "unknown"
+
+
+def cpu_baseline(wl: dict, tiny: dict, envs_per_worker: int = 64, cpu_seconds: float = 18.0) -> dict:
+    """The oracle as it stands, on the host cores: the tiny workload in full
+    (16 envs x 1000 steps) and a sample of the headline workload on one pinned
+    core, then the headline sample split over every core of this process's
+    affinity set (about `cpu_seconds` of CPU work in all).  The oracle's own
+    column flags over the sample give the flagged fractions of the workload."""
+    import oracle
+    oracle.build()
+    cfg = wl["cfg"]
+    cores = sorted(os.sched_getaffinity(0))
+    n_workers = len(cores)
+    prev = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {cores[0]})
+    try:
+        # the tiny workload in full, one core
+        tn, ts = tiny["n_envs"], tiny["steps"]
+        t0 = time.perf_counter()
+        tdone, _ = _oracle_chunk((tiny["cfg"], W.seeds(tiny["number"], tn),
+                                  W.actions(tiny["number"], ts, tn, tiny["cfg"]["n_actions"])))
+        dt_tiny = time.perf_counter() - t0
+        # a one-core sample of the headline workload (also sizes the all-core sample)
+        probe_steps = 300
+        seeds1 = W.seeds(wl["number"], envs_per_worker)
+        acts1 = W.actions(wl["number"], probe_steps, envs_per_worker, cfg["n_actions"])
+        t0 = time.perf_counter()
+        one, _ = _oracle_chunk((cfg, seeds1, acts1))
+        dt1 = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, prev)
+    one_core = one / dt1
+    steps = max(100, int(cpu_seconds * one_core / (n_workers * envs_per_worker)))
+    seeds = W.seeds(wl["number"], envs_per_worker * n_workers)
+    acts = W.actions(wl["number"], steps, envs_per_worker * n_workers, cfg["n_actions"])
+    chunks = [(cfg, seeds[k * envs_per_worker:(k + 1) * envs_per_worker],
+               np.ascontiguousarray(acts[:, k * envs_per_worker:(k + 1) * envs_per_worker]))
+              for k in range(n_workers)]
+    ctx = mp.get_context("spawn")
+    pool = ctx.Pool(n_workers)
+    try:
+        pool.map(_oracle_chunk, chunks[:1])          # start-up outside the timing
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_chunk, chunks)
+        dtn = time.perf_counter() - t0
+    finally:
+        pool.close()
+        pool.join()
+    tot = sum(r[0] for r in res)
+    cnt = {k: sum(r[1][k] for r in res) for k in res[0][1]}
+    flags = {"columns": cnt["columns"], "flagged_frac": cnt["flagged"] / max(1, cnt["columns"]),
+             "f1_frac": cnt["f1"] / max(1, cnt["columns"]),
+             "steps_flagged_frac": cnt["steps_flagged"] / max(1, tot),
+             "sample": f"the oracle's own trajectories of {n_workers * envs_per_worker} envs x "
+                       f"{steps} steps of {wl['name']}"}
     return {"value": tot / dtn, "unit": "env-steps/s", "cores": n_workers, "kind": "oracle",
-            "sample": (f"{wl['name']}: {envs_per_worker} envs x {steps} steps per worker "
-                       f"(step + full render, FP64 C oracle, gcc -O2); one pinned core: "
-                       f"{one / dt1:.0f} env-steps/s; cpu: {model}"),
-            "one_core": one / dt1}
+            "sample": (f"{wl['name']}: {envs_per_worker} envs x {steps} steps per worker on each of "
+                       f"{n_workers} cores (step + full render, FP64 C oracle, gcc -O2); one pinned "
+                       f"core: {one_core:.0f} env-steps/s ({envs_per_worker} envs x {probe_steps} "
+                       f"steps); {tiny['name']} in full on one core: {tdone / dt_tiny:.0f} "
+                       f"env-steps/s; cpu: {_cpu_model()}"),
+            "one_core": one_core, "tiny_one_core": tdone / dt_tiny, "flags": flags}
 
 
 def batch_form(jx, torch, launches: list[dict], rollouts: int = 2) -> dict:
@@ -287,6 +317,12 @@ def main() -> int:
     slots = 1 if args.single_slot else RING
     obs = torch.empty(slots * ob, dtype=torch.uint8, device=env.dev)
     env.reset(obs[:ob])
+    # Episode clocks staggered (env i starts at t = i mod cap): the envs then
+    # reach the cap evenly, n / cap of them reset in every step, as in the
+    # steady state of a long run, so resets fall inside the timed steps at any
+    # step count.
+    cap = cfg["episode_cap"]
+    env.set_state({"t": (np.arange(n) % cap).astype(np.uint32)})
     acts = torch.from_numpy(W.actions(wl["number"], Wu + K, n, cfg["n_actions"])).to(env.dev)
     rew = torch.empty(RING * n, dtype=torch.float32, device=env.dev)
     done = torch.empty(RING * n, dtype=torch.uint8, device=env.dev)
@@ -325,6 +361,7 @@ def main() -> int:
             env.rollout(acts[:T], obs, rew, done, T, obs_stride=ob if slots > 1 else 0, graph=True)
     run(0, Wu)
     torch.cuda.synchronize()
+    ep_before = int(env.get_state()["episode"].astype(np.int64).sum())
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -335,6 +372,7 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     ms = e0.elapsed_time(e1)
+    episodes_timed = int(env.get_state()["episode"].astype(np.int64).sum()) - ep_before
     sec = ms / 1e3
     rate = n * K / sec
     # The fused form runs one kernel per ring chunk (up to 128 steps); the
@@ -493,7 +531,6 @@ def main() -> int:
         # previous actions): NCHW float32 and u8, NHWC bfloat16
         buffers = [buffer_rate(1, 2), buffer_rate(0, 1), buffer_rate(1, 0)]
         keydoor = keydoor_rate()
-    S = env.get_state()
     line = {
         "metric": "rendered env-steps/s @4096 envs 64x64 RGB; served p50/p99 step latency vs plain",
         "value": rate,
@@ -528,7 +565,8 @@ def main() -> int:
         "training_buffer": buffers,
         "keydoor_workload": keydoor,
         "obs_write_gbs": ab["obs"] * n * K / sec / 1e9,
-        "episodes_completed": int(S["episode"].astype(np.int64).sum()),
+        "episodes_completed_in_timed_steps": episodes_timed,
+        "episode_clocks": "staggered: env i starts at t = i mod cap",
         "wall_s": wall,
     }
     env.close()
@@ -562,7 +600,8 @@ def main() -> int:
                                   "plain_env_steps_per_s": runs[1]["env_steps_per_s"]}
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle on the host cores)")
-        line["cpu_baseline"] = cpu_baseline(wl)
+        line["cpu_baseline"] = cpu_baseline(wl, W.TINY)
+        line["flagged_columns"] = line["cpu_baseline"]["flags"]
     print(json.dumps(line), flush=True)
     return 0
 

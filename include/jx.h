@@ -5,7 +5,7 @@
  *
  * The method (JAXenstein, Tao & Konidaris): every environment is a partially
  * observable first-person task on a tile map with discrete actions and pixel
- * observations (abstract, Sec. 1, Sec. 3.3).  Each frame is drawn by casting one
+ * observations (abstract, Sec. 1; partial observability, Sec. 1).  Each frame is drawn by casting one
  * ray per image column to its first wall, found by DDA marching along tile
  * boundaries (Sec. 2.1), over a tile-map world (Sec. 2.2, Sec. 3.2, Table 2);
  * objects are fixed billboard sprites (Fig. 1).  Frames are rendered natively
@@ -146,16 +146,20 @@ typedef struct {
   int32_t count;    /* number of elements */
 } jx_field;
 
+/* ABI version of the library (JX_ABI_VERSION it was built with) and the
+ * calling thread's last error message (library plumbing; not in the paper). */
 int32_t jx_abi_version(void);
 const char* jx_last_error(void);
 
-/* Bytes of device workspace needed for n_envs environments.  cfg_index[i]
+/* Bytes of device workspace needed for n_envs environments (the library's
+ * memory plan; not in the paper).  cfg_index[i]
  * selects cfgs[cfg_index[i]]; cfg_index may be NULL when n_cfgs == 1.
  * Returns 0 on invalid arguments. */
 size_t jx_workspace_bytes(int32_t n_envs, const jx_env_cfg* cfgs, int32_t n_cfgs,
                           const int32_t* cfg_index);
 
-/* Creates a context on `device`, enqueueing on `hip_stream` (a hipStream_t;
+/* Creates a context (library plumbing; not in the paper) on `device`,
+ * enqueueing on `hip_stream` (a hipStream_t;
  * NULL = the default stream).  `workspace_dev` is caller-owned device memory of
  * ws_bytes bytes, 256-byte aligned; it holds all environment state (SoA), maps
  * and tables and must outlive the context. */
@@ -163,15 +167,22 @@ jx_status jx_create(jx_ctx** out, int32_t device, void* hip_stream, void* worksp
                     size_t ws_bytes);
 void jx_destroy(jx_ctx* ctx);
 
-/* Starts episode 0 of every env: generates each env's maze from seeds_host[i]
+/* Starts episode 0 of every env (the paper's tasks: tile-map worlds of
+ * Sec. 2.2 and Sec. 3.2, the navigation and key-door tasks of Table 1, the
+ * ASCII symbols of Table 2; the per-episode spawn, goal, door and key draws
+ * are this library's reading).  Generates each env's maze from seeds_host[i]
  * on the host, uploads maps and tables, and runs the episode reset on the
- * device.  When obs_dev is not NULL the first frames are rendered into it.
+ * device.  cfgs_host[n_cfgs] are the configurations, cfg_index_host[n] (NULL
+ * when n_cfgs == 1) picks env i's.  Errors: JX_EINVAL for a bad configuration
+ * or ASCII map (message in jx_last_error), JX_ENOMEM when the context's
+ * workspace is smaller than jx_workspace_bytes(), JX_EDEVICE on a HIP error.  When obs_dev is not NULL the first frames are rendered into it.
  * n_envs may be 0 (every later call is then a no-op).  Synchronous: returns
  * after the reset kernel has finished. */
 jx_status jx_reset(jx_ctx* ctx, int32_t n_envs, const uint64_t* seeds_host,
                    const jx_env_cfg* cfgs_host, int32_t n_cfgs, const int32_t* cfg_index_host,
                    uint8_t* obs_dev);
 
+/* Sizes of the batch (library plumbing; not in the paper). */
 int32_t jx_num_envs(const jx_ctx* ctx);
 /* Total observation bytes of one step (sum over envs). */
 int64_t jx_obs_bytes(const jx_ctx* ctx);
@@ -179,7 +190,12 @@ int64_t jx_obs_bytes(const jx_ctx* ctx);
  * buffer; offsets_host[n] = jx_obs_bytes(). */
 jx_status jx_obs_offsets(const jx_ctx* ctx, int64_t* offsets_host);
 
-/* One batched transition and render.  actions_dev[n] uint8 (values >= n_actions
+/* One batched transition and render of every env: a first-person task with
+ * discrete actions and pixel observations (Sec. 1, Sec. 3.2), stepped as one
+ * batch (the paper vectorises envs with vmap, Sec. 1, Sec. 3.1); each frame is
+ * drawn by one DDA ray per image column (Sec. 2.1) at the training resolution
+ * (Sec. 3.1, App. A.1).  The action rules, rewards and auto-reset are this
+ * library's readings.  actions_dev[n] uint8 (values >= n_actions
  * are counted no-ops); obs_dev receives jx_obs_bytes() bytes (4-byte aligned;
  * 16-byte aligned for the floating formats); reward_dev[n] float32; done_dev[n]
  * uint8.  prev_action_dev (nullable) [n] uint8 receives the previous action to
@@ -189,7 +205,10 @@ jx_status jx_obs_offsets(const jx_ctx* ctx, int64_t* offsets_host);
 jx_status jx_step(jx_ctx* ctx, const uint8_t* actions_dev, uint8_t* obs_dev, float* reward_dev,
                   uint8_t* done_dev, uint8_t* prev_action_dev);
 
-/* T consecutive steps.  actions_dev[T][n]; step t writes its frames at
+/* T consecutive steps (the paper's learner collects 128-step rollouts of
+ * vmapped envs, Sec. 3.1, App. A.2 and the PPO hyperparameter table; graph
+ * capture and the fused launch are this library's).  actions_dev[T][n]; step t
+ * writes its frames at
  * obs_dev + t*obs_stride (obs_stride >= jx_obs_bytes(), or 0 to write every
  * step into the same frame buffer), rewards at reward_dev + t*n, dones at
  * done_dev + t*n and, when prev_action_dev is not NULL, previous actions (as in
@@ -211,11 +230,15 @@ jx_status jx_rollout(jx_ctx* ctx, int32_t T, const uint8_t* actions_dev, uint8_t
                      int64_t obs_stride, float* reward_dev, uint8_t* done_dev,
                      uint8_t* prev_action_dev, int32_t flags);
 
-/* Renders the current state without stepping.  obs_dev may be NULL;
+/* Renders the current state without stepping: one ray per image column to
+ * the first blocking tile by DDA over tile boundaries, perpendicular distance,
+ * column fill by hit tile and side (Sec. 2.1), billboard sprites (Fig. 1
+ * caption).  obs_dev may be NULL;
  * column_debug_dev (nullable) receives jx_col_debug[n][max obs_w]. */
 jx_status jx_render(jx_ctx* ctx, uint8_t* obs_dev, jx_col_debug* column_debug_dev);
 
-/* State image: every per-env array, the maps and the configuration table, as
+/* State image (checkpoint format of this library; not in the paper): every
+ * per-env array, the maps and the configuration table, as
  * one host buffer of jx_state_bytes() bytes.  jx_set_state() accepts only an
  * image taken from a context reset with the same envs and configurations.
  * Both synchronise the context's stream. */
@@ -224,10 +247,13 @@ jx_status jx_state_layout(const jx_ctx* ctx, jx_field* fields, int32_t cap, int3
 jx_status jx_get_state(const jx_ctx* ctx, void* host_buf, size_t bytes);
 jx_status jx_set_state(jx_ctx* ctx, const void* host_buf, size_t bytes);
 
+/* Launch mapping of later steps (this library's batching forms; results do
+ * not depend on it).  JX_EINVAL for a mapping outside the limits above. */
 jx_status jx_set_launch(jx_ctx* ctx, const jx_launch* launch);
 jx_status jx_get_launch(const jx_ctx* ctx, jx_launch* launch);
 
-/* Autotuner: times every candidate mapping over `iters` steps driven by
+/* Autotuner (this library's; the paper's batching is jit + vmap, Sec. 1,
+ * Sec. 3.1): times every candidate mapping over `iters` steps driven by
  * actions_dev[iters][n], writing frames into obs_scratch_dev (jx_obs_bytes()
  * bytes), checks that each candidate's frames, rewards, dones and state are
  * bit-identical to the default mapping's, and selects the fastest.  The env
@@ -237,14 +263,19 @@ jx_status jx_get_launch(const jx_ctx* ctx, jx_launch* launch);
 jx_status jx_autotune(jx_ctx* ctx, const uint8_t* actions_dev, int32_t iters,
                       uint8_t* obs_scratch_dev, const char* cache_path, jx_launch* chosen);
 
+/* Waits for the context's stream; JX_EDEVICE reports a device fault of any
+ * earlier call (library plumbing; not in the paper). */
 jx_status jx_sync(jx_ctx* ctx);
 
-/* Host only (no device): the N x N tile grid (0 floor, 1 wall) that jx_reset
- * builds for `seed` under `cfg`. */
+/* Host only (no device): the N x N tile grid (0 floor, 1 wall; tile bytes of
+ * an ASCII map) that jx_reset builds for `seed` under `cfg` (the tile-map
+ * worlds of Sec. 2.2 and Table 2; the seeded maze is this library's reading). */
 jx_status jx_make_layout(uint64_t seed, const jx_env_cfg* cfg, uint8_t* grid_host);
 
 /* ---------------------------------------------------------------------------
- * Serving: a request loop holding many clients' environments resident on one
+ * Serving (not in the paper: this library's serving form of the same step and
+ * render; the paper measures steps/s and training throughput only, Sec. 3.1).
+ * A request loop holding many clients' environments resident on one
  * device.  Clients open env batches of any size and configuration; requests
  * (one step of one client) that are ready are coalesced into shared persistent
  * launches spread over n_streams streams, so that requests arriving while

@@ -110,6 +110,9 @@ DevCfg derive_cfg(const jx_env_cfg& c) {
   d.tanH = (float)std::tan((double)c.fov_deg * M_PI / 360.0);
   d.inv_tanH = (float)(1.0 / (double)d.tanH);
   d.inv_w = (float)(1.0 / (double)c.obs_w);
+  const double q = std::tan((double)c.fov_deg * M_PI / 360.0) / (double)c.obs_w;
+  d.ray_q_hi = (float)q;
+  d.ray_q_lo = (float)(q - (double)d.ray_q_hi);
   d.shade_levels = c.shade_levels;
   d.shade_scale = c.shade_levels > 0 ? (float)((double)c.shade_levels / (double)c.shade_dist) : 0.f;
   d.shade_mul = c.shade_levels > 0 ? (65536u + (uint32_t)c.shade_levels - 1u) / (uint32_t)c.shade_levels : 0u;

@@ -37,7 +37,10 @@ struct DevCfg {
   float move, turn, pr2, r_goal;
   float r_key, tanH, inv_tanH, inv_w;  // 1/tanH and 1/obs_w, rounded to float
   int32_t ascii;  // 1: the layout is an ASCII map (doors, keys, candidates)
-  int32_t pad3[3];
+  // tan(fov/2) / obs_w in double, split into two floats (hi + lo, 48 bits):
+  // column c's ray is dir + (2c + 1 - obs_w) * ray_q * right
+  float ray_q_hi, ray_q_lo;
+  int32_t pad3;
 };
 static_assert(sizeof(DevCfg) == 96, "DevCfg layout");
 

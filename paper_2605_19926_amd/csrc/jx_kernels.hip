@@ -127,6 +127,11 @@ __device__ __forceinline__ uint32_t uniform_u(uint32_t v) {
 __device__ __forceinline__ float uniform_f(float v) {
   return __uint_as_float((uint32_t)__builtin_amdgcn_readfirstlane((int)__float_as_uint(v)));
 }
+__device__ __forceinline__ double uniform_d(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = uniform_u((uint32_t)b), hi = uniform_u((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
 // ---- SplitMix64 (Steele, Lea & Flood 2014) --------------------------------------
 __device__ __forceinline__ uint64_t sm_next(uint64_t& s) {
@@ -547,18 +552,19 @@ struct ColDbg {
 
 // Casts the env's columns and reduces each to a span record in lcol (and
 // writes debug records when asked).
-// sn, cs: sine and cosine of the heading.
+// dsn, dcs: sine and cosine of the heading in double.
 template <bool ASC>
 __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int lane, uint8_t* lmap,
                                const uint32_t* lclr,
-                               uint32_t* lcol, float x, float y, float sn, float cs, int goal,
+                               uint32_t* lcol, float x, float y, double dsn, double dcs, int goal,
                                int door, int key, uint32_t fl, int nd, int dec0, int dec1,
                                uint32_t doors, int ak0, int ak1, int ak2) {
   const int N = cf.side, H = cf.obs_h, W = cf.obs_w, K = cf.n_colors, S_lv = cf.shade_levels;
   // the shut locked door blocks rays like a wall (tile id `shut`, -1 if none)
   const int shut = (door >= 0 && !(fl & FL_DOOR_OPEN)) ? door : -1;
-  const float tanH = cf.tanH;
-  const float px = -sn * tanH, py = cs * tanH;
+  const float sn = (float)dsn, cs = (float)dcs;
+  // column c's ray offset along `right` is (2c + 1 - W) * q, q = tanH / W
+  const double rq = (double)cf.ray_q_hi + (double)cf.ray_q_lo;
 
   // Sprites in fixed slots, in painting-index order: key, goal, decor 0, decor 1
   // (ASCII maps: red, blue, yellow key, goal).  Empty slots are skipped, which
@@ -597,29 +603,37 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
   const float halfH = (float)(H >> 1);
   const float INF = __builtin_huge_valf();
   for (int col = lane; col < W; col += 64) {
-    const float camX = (float)(2 * col + 1 - W) * cf.inv_w;
-    const float rx = fmaf(camX, px, cs);
-    const float ry = fmaf(camX, py, sn);
+    // The ray components are formed in double and rounded once: dir and the
+    // column's offset along `right` can nearly cancel, and a float sum would
+    // then lose most of the component's digits.  Each float component is
+    // within half an ulp of the exact one.
+    const double k = (double)(2 * col + 1 - W) * rq;
+    const float rx = (float)fma(k, -dsn, dcs);
+    const float ry = (float)fma(k, dcs, dsn);
     const int ix = ix0, iy = iy0;
     const int stx = rx > 0.f ? 1 : -1, sty = ry > 0.f ? 1 : -1;
     const float Xn = (float)(rx > 0.f ? ix + 1 : ix);
     const float Yn = (float)(ry > 0.f ? iy + 1 : iy);
     const float ivx = __builtin_amdgcn_rcpf(rx), ivy = __builtin_amdgcn_rcpf(ry);
-    // ray parameter of the next x / y grid line, and its step per line
-    float tx = rx != 0.f ? (Xn - x) * ivx : INF;
-    float ty = ry != 0.f ? (Yn - y) * ivy : INF;
+    // Ray parameter of the k-th x / y grid line ahead: t0 + k |1/r|, one fused
+    // multiply-add from the crossing count (Xn - x is exact, 1/r within an
+    // ulp), so every crossing parameter is within a few float ulps of the
+    // exact one whatever the walk's length.
+    const float t0x = rx != 0.f ? (Xn - x) * ivx : INF;
+    const float t0y = ry != 0.f ? (Yn - y) * ivy : INF;
     const float dtx = rx != 0.f ? fabsf(ivx) : 0.f, dty = ry != 0.f ? fabsf(ivy) : 0.f;
+    float kx = 0.f, ky = 0.f;
+    float tx = t0x, ty = t0y;
     float tst = INF;
     int side = 0, hit = -1, cell = 1;
     uint32_t hv = 1u;  // tile byte of the hit
     // Branch-free walk in batches: the sequence of tiles a ray crosses does
     // not depend on the map, only where it stops does.  Each batch computes
     // the next kDdaBatch crossings (one grid line each: the tile index moves
-    // by +-1 on an x crossing, +-N on a y crossing, and that axis's line
-    // parameter advances by its spacing |1/r|; over at most 4N+8 crossings the
-    // accumulated rounding stays a few ulp), issues their LDS reads
-    // together and keeps the first blocking one, so a lane waits for one LDS
-    // round trip per batch instead of one per crossing.  The border of
+    // by +-1 on an x crossing, +-N on a y crossing, and that axis's crossing
+    // count by one), issues their LDS reads together and keeps the first
+    // blocking one, so a lane waits for one LDS round trip per batch instead
+    // of one per crossing.  The border of
     // blocking tiles (checked on the host) stops every walk inside the map;
     // crossings past the stop are discarded and read a clamped address.
     const int dy = sty * N, NN = N * N;
@@ -636,8 +650,10 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
         ts[u] = sx ? tx : ty;
         sd[u] = !sx;
         id += sx ? stx : dy;
-        tx = sx ? tx + dtx : tx;
-        ty = sx ? ty : ty + dty;
+        kx = sx ? kx + 1.f : kx;
+        ky = sx ? ky : ky + 1.f;
+        tx = fmaf(kx, dtx, t0x);
+        ty = fmaf(ky, dty, t0y);
         ids[u] = id;
       }
       // bit u: crossing u stops the walk (blocking tile, shut door, or off the map)
@@ -833,6 +849,7 @@ struct EnvOut {
   uint32_t t, ep, fl, nd, ev, done, doors;
   uint32_t prev;  // previous action beside the frame (n_actions: none)
   int goal, door, key, dec0, dec1;
+  double sn, cs;  // sine and cosine of th, in double
 };
 
 // Inputs of one env-step, loaded ahead of use: the configuration and state
@@ -847,6 +864,7 @@ struct EnvIn {
   int goal, door, key, dec0, dec1, nd;
   int ak0, ak1, ak2;  // ASCII maps: key tiles (constant per env)
   uint64_t seed;
+  double sn, cs;      // sine and cosine of th, in double
   uint32_t map[kMapWords];
 };
 
@@ -879,6 +897,7 @@ __device__ __forceinline__ void load_env(const DevState& S, int env, int lane, E
   in.ak0 = S.akey[3 * env];
   in.ak1 = S.akey[3 * env + 1];
   in.ak2 = S.akey[3 * env + 2];
+  sincos((double)in.th, &in.sn, &in.cs);
 }
 
 // Bit mask of the map's locked doors of colour c (door type c), gathered by
@@ -934,8 +953,10 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   float reward = 0.f;
   uint32_t ev = 0;
   bool done = false;
-  float sn, cs;
-  sincosf(th, &sn, &cs);
+  // sine and cosine of the heading in double (from the env's inputs; they
+  // are recomputed only when the heading changes)
+  double dsn = in.sn, dcs = in.cs;
+  const float sn = (float)dsn, cs = (float)dcs;
   bool heading_changed = false;
   uint32_t prev = (uint32_t)cf.n_actions;
   if (mode == MODE_STEP) {
@@ -1062,9 +1083,9 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
     if (done) ev |= EV_RESET;
     heading_changed = true;
   }
-  if (heading_changed) sincosf(th, &sn, &cs);
+  if (heading_changed) sincos((double)th, &dsn, &dcs);
   if (io.obs || io.dbg)
-    render_columns<ASC>(cf, io, env, lane, lmap, lclr, lcol, x, y, sn, cs, goal, door, key, fl, nd, dec0, dec1,
+    render_columns<ASC>(cf, io, env, lane, lmap, lclr, lcol, x, y, dsn, dcs, goal, door, key, fl, nd, dec0, dec1,
                    doors, in.ak0, in.ak1, in.ak2);
   o.obs_off = 0;  // set by the caller (obs_off_of), outside any step loop
   o.env = env;
@@ -1088,6 +1109,8 @@ __device__ void produce_env(const EnvIn<MAXN>& in, const DevState& S, const DevI
   o.dec1 = dec1;
   o.doors = doors;
   o.prev = prev;
+  o.sn = dsn;
+  o.cs = dcs;
 }
 
 // Scalar results of one env-step, stored by lane 0 with vector stores.
@@ -1386,6 +1409,8 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
         in.dec0 = (int)uniform_u((uint32_t)o.dec0);
         in.dec1 = (int)uniform_u((uint32_t)o.dec1);
         in.doors = uniform_u(o.doors);
+        in.sn = uniform_d(o.sn);
+        in.cs = uniform_d(o.cs);
       }
     }
     if (lane == 0 && T > 0) {

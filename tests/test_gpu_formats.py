@@ -71,11 +71,11 @@ def test_reset_and_step_frames_against_oracle(name, base, n, layout, dtype):
     grids = [U.oracle_maze(cfg, s) for s in seeds]
     stats = U.FrameStats()
     obs0 = env.obs0.cpu().numpy()
+    conv = lambda f: oracle_hwc(f, layout, dtype)   # noqa: E731
     for i in range(n):
         o = orc.reset(grids[i], oc, int(seeds[i]), 0)
-        oo, cols = orc.render(grids[i], oc, o)
-        U.compare_frame(stats, gpu_frame(obs0, env, i, cfg), oracle_hwc(oo, layout, dtype), cols,
-                        tag=f"reset env {i}")
+        U.check_frame(stats, gpu_frame(obs0, env, i, cfg), grids[i], oc, o, tag=f"reset env {i}",
+                      convert=conv)
     # steps: the frame is the render of the stored post-step state
     rng = np.random.default_rng(7)
     obs = torch.empty(env.obs_bytes, dtype=torch.uint8, device=env.dev)
@@ -91,9 +91,8 @@ def test_reset_and_step_frames_against_oracle(name, base, n, layout, dtype):
         for i in range(n):
             assert pv[i] == orc.prev_action(oc, int(acts[i]), int(done[i])), f"step {t} env {i}"
             st = orc.state_from(U.gpu_state_dict(S, i))
-            oo, cols = orc.render(grids[i], oc, st)
-            U.compare_frame(stats, gpu_frame(on, env, i, cfg), oracle_hwc(oo, layout, dtype), cols,
-                            tag=f"step {t} env {i}")
+            U.check_frame(stats, gpu_frame(on, env, i, cfg), grids[i], oc, st, tag=f"step {t} env {i}",
+                          convert=conv)
     # render without stepping: the frame of the current state, as the last step returned it
     again = torch.zeros_like(obs)
     env.render(again)

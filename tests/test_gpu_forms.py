@@ -186,16 +186,17 @@ def test_mixed_shapes_batch_identical_and_oracle():
     for i in pick:
         i = int(i)
         c = cfgs[idx[i]]
-        oo, cols = orc.render(grids[i], orc.make_cfg(c), orc.state_from(states[i]))
-        U.compare_frame(stats, U.frame_of(o1, env.obs_offsets, i, c["obs_h"], c["obs_w"]), oo, cols,
-                        tag=f"render env {i}")
+        oc = orc.make_cfg(c)
+        U.check_frame(stats, U.frame_of(o1, env.obs_offsets, i, c["obs_h"], c["obs_w"]), grids[i], oc,
+                      orc.state_from(states[i]), tag=f"render env {i}")
+        g_after = U.gpu_state_dict(S, i)
         skip, errs, o = U.compare_step(states[i], c, seeds[i], grids[i], acts[i],
-                                       U.gpu_state_dict(S, i), rew[i], done[i], S["events"][i])
+                                       g_after, rew[i], done[i], S["events"][i])
         assert skip or not errs, (i, errs)
-        if not skip and U.same_pose(U.gpu_state_dict(S, i), U.round32(o)):
-            oo, cols = orc.render(grids[i], orc.make_cfg(c), orc.state_from(U.round32(o)))
-            U.compare_frame(stats, U.frame_of(o2, env.obs_offsets, i, c["obs_h"], c["obs_w"]), oo,
-                            cols, tag=f"step env {i}")
+        # the step's frame is the render of the post-step state the GPU stored
+        U.check_frame(stats, U.frame_of(o2, env.obs_offsets, i, c["obs_h"], c["obs_w"]), grids[i], oc,
+                      orc.state_from(g_after), tag=f"step env {i}")
+    stats.report(f"render+one-step/{W.BATCH['name']}-2048")
     assert not stats.mismatch, stats.mismatch[:10]
     assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
     env.close()

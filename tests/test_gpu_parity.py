@@ -58,15 +58,15 @@ def test_reset_state_and_first_frame(wl, n_check):
         o = orc.reset(grid, orc.make_cfg(cfg), int(seeds[i]), 0).as_dict()
         errs = U.compare_reset_state(U.gpu_state_dict(S, i), o)
         assert not errs, f"env {i}: {errs}"
-        oo, cols = orc.render(grid, orc.make_cfg(cfg), orc.state_from(o))
         g = U.frame_of(obs, env.obs_offsets, i, cfg["obs_h"], cfg["obs_w"])
-        U.compare_frame(stats, g, oo, cols, D[i], tag=f"env {i}")
+        U.check_frame(stats, g, grid, orc.make_cfg(cfg), orc.state_from(o), D[i], tag=f"env {i}")
+    stats.report(f"reset/{wl['name']}")
     assert not stats.mismatch, stats.mismatch[:10]
     assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
     env.close()
 
 
-def _one_step_case(cfg, n, number, n_check, launch=None, seed_rng=7, invalid_frac=0.03):
+def _one_step_case(cfg, n, number, n_check, launch=None, seed_rng=7, invalid_frac=0.03, name=None):
     import torch
     seeds = W.seeds(number, n)
     env = U.env_of(cfg, seeds, obs=False)
@@ -106,9 +106,9 @@ def _one_step_case(cfg, n, number, n_check, launch=None, seed_rng=7, invalid_fra
     obs_np = obs.cpu().numpy()
     stats = U.FrameStats()
     skipped = 0
-    rounding = 0
     errors = []
     n_done = 0
+    oc = orc.make_cfg(cfg)
     for i in pick:
         i = int(i)
         g_after = U.gpu_state_dict(S, i)
@@ -116,24 +116,16 @@ def _one_step_case(cfg, n, number, n_check, launch=None, seed_rng=7, invalid_fra
                                        g_after, rew[i], done[i], S["events"][i])
         if skip:
             skipped += 1
-            continue
-        errors += [f"env {i}: {e}" for e in errs]
-        n_done += int(done[i])
-        if errs:
-            continue
-        # The frame is the render of the post-step state as stored (float32).  It
-        # is compared when the oracle's next pose, rounded to float32, is the
-        # GPU's pose; a pose one rounding apart (the float32 move landed on the
-        # other side of a rounding midpoint) is counted instead.
-        o32 = U.round32(o)
-        if not U.same_pose(g_after, o32):
-            rounding += 1
-            continue
-        oo, cols = orc.render(grids[i], orc.make_cfg(cfg), orc.state_from(o32))
+        else:
+            errors += [f"env {i}: {e}" for e in errs]
+            n_done += int(done[i])
+        # The frame the step returned is the render of the post-step state the
+        # GPU stored (float32); the oracle renders that same state (shared-state
+        # check), so every sampled frame is compared, flagged steps included.
         g = U.frame_of(obs_np, env.obs_offsets, i, cfg["obs_h"], cfg["obs_w"])
-        U.compare_frame(stats, g, oo, cols, D[i], tag=f"env {i}")
+        U.check_frame(stats, g, grids[i], oc, orc.state_from(g_after), D[i], tag=f"env {i}")
+    stats.report(f"one-step/{name or cfg.get('obs_w')}")
     assert skipped <= max(2, len(pick) // 50), f"too many flagged steps: {skipped}"
-    assert rounding <= max(3, len(pick) // 10), f"poses one rounding apart: {rounding}"
     assert not errors, errors[:10]
     assert not stats.mismatch, stats.mismatch[:10]
     assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
@@ -143,7 +135,7 @@ def _one_step_case(cfg, n, number, n_check, launch=None, seed_rng=7, invalid_fra
     return n_done, stats
 
 
-def _render_case(cfg, n, number, n_check, seed_rng=3, launch=None):
+def _render_case(cfg, n, number, n_check, seed_rng=3, launch=None, name=None):
     """Shared input state set into the GPU, rendered by both sides."""
     import torch
     seeds = W.seeds(number, n)
@@ -166,11 +158,13 @@ def _render_case(cfg, n, number, n_check, seed_rng=3, launch=None):
     D = _dbg_np(dbg, env)
     obs_np = obs.cpu().numpy()
     stats = U.FrameStats()
+    oc = orc.make_cfg(cfg)
     for i in pick:
         i = int(i)
-        oo, cols = orc.render(grids[i], orc.make_cfg(cfg), orc.state_from(states[i]))
         g = U.frame_of(obs_np, env.obs_offsets, i, cfg["obs_h"], cfg["obs_w"])
-        U.compare_frame(stats, g, oo, cols, D[i], tag=f"env {i}")
+        U.check_frame(stats, g, grids[i], oc, orc.state_from(states[i]), D[i], tag=f"env {i}")
+    if name:
+        stats.report(f"render/{name}")
     assert not stats.mismatch, stats.mismatch[:10]
     assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
     env.close()
@@ -181,7 +175,7 @@ def _render_case(cfg, n, number, n_check, seed_rng=3, launch=None):
                                           (W.KEYDOOR, 8192, 160), (W.ASCII, 4096, 256),
                                           (W.ASCII_TINY, 16, 16)])
 def test_render_shared_state(wl, n, n_check):
-    _render_case(wl["cfg"], n, wl["number"], n_check)
+    _render_case(wl["cfg"], n, wl["number"], n_check, name=wl["name"])
 
 
 @pytest.mark.parametrize("wl,n,n_check,levels,dist", [(W.SCALE, 4096, 256, 8, 12.0),
@@ -189,32 +183,46 @@ def test_render_shared_state(wl, n, n_check):
                                                         (W.TINY, 16, 16, 16, 3.0)])
 def test_render_shared_state_distance_shading(wl, n, n_check, levels, dist):
     cfg = dict(wl["cfg"], shade_levels=levels, shade_dist=dist)
-    stats = _render_case(cfg, n, wl["number"], n_check, seed_rng=41)
+    stats = _render_case(cfg, n, wl["number"], n_check, seed_rng=41, name=f"{wl['name']}-shaded{levels}")
     assert stats.cols >= n_check * cfg["obs_w"]
+
+
+@pytest.mark.parametrize("wl", [W.OPEN64, W.PILLARS64])
+def test_long_rays_render_and_one_step(wl):
+    # 64-side maps where rays cross up to ~90 tiles (128 columns each): the
+    # longest walks the kernel makes, where each crossing parameter comes from
+    # the most line counts
+    stats = _render_case(wl["cfg"], wl["n_envs"], wl["number"], wl["n_envs"], seed_rng=17,
+                         name=wl["name"])
+    assert stats.cols == wl["n_envs"] * 128
+    for k in range(3):
+        _one_step_case(wl["cfg"], wl["n_envs"], wl["number"], wl["n_envs"], seed_rng=90 + k,
+                       name=wl["name"])
 
 
 def test_one_step_tiny_all_envs():
     for k in range(8):
-        _one_step_case(W.TINY["cfg"], 16, W.TINY["number"], 16, seed_rng=100 + k)
+        _one_step_case(W.TINY["cfg"], 16, W.TINY["number"], 16, seed_rng=100 + k, name=W.TINY["name"])
 
 
 def test_one_step_scale_full_size_sampled():
     # the headline workload's full batch, plain per-step mapping (the timed
     # fused launch is checked by test_headline_fused_rollout_full_size)
     _one_step_case(W.SCALE["cfg"], 4096, W.SCALE["number"], 160,
-                   launch=dict(form=0, waves_per_group=1, groups_per_cu=4, store_mode=0))
+                   launch=dict(form=0, waves_per_group=1, groups_per_cu=4, store_mode=0),
+                   name=W.SCALE["name"])
 
 
 def test_one_step_ascii_maps():
     # every Table 2 symbol: keys by colour, locked and unlocked doors (random
     # open/taken states), candidates, coloured walls
-    _one_step_case(W.ASCII["cfg"], 4096, W.ASCII["number"], 200, seed_rng=61)
+    _one_step_case(W.ASCII["cfg"], 4096, W.ASCII["number"], 200, seed_rng=61, name=W.ASCII["name"])
     for k in range(4):
         _one_step_case(W.ASCII_TINY["cfg"], 16, W.ASCII_TINY["number"], 16, seed_rng=70 + k)
 
 
 def test_one_step_keydoor_sampled():
-    _one_step_case(W.KEYDOOR["cfg"], 8192, W.KEYDOOR["number"], 96)
+    _one_step_case(W.KEYDOOR["cfg"], 8192, W.KEYDOOR["number"], 96, name=W.KEYDOOR["name"])
 
 
 @pytest.mark.parametrize("side,hw", [(5, (2, 4)), (64, (128, 128)), (9, (84, 84)), (33, (32, 32)),
@@ -222,7 +230,7 @@ def test_one_step_keydoor_sampled():
 def test_one_step_shape_extremes(side, hw):
     cfg = W.env_cfg(side=side, loop_frac=0.1, key_door=1 if side >= 9 else 0, goal_sprite=1,
                     max_decor=2, obs_h=hw[0], obs_w=hw[1], episode_cap=64)
-    _one_step_case(cfg, 48, 11, 48, seed_rng=side)
+    _one_step_case(cfg, 48, 11, 48, seed_rng=side, name=f"side{side}-{hw[0]}x{hw[1]}")
 
 
 def test_persistent_form_matches_plain_one_step():
@@ -268,7 +276,7 @@ def test_headline_fused_rollout_full_size():
     oc = orc.make_cfg(cfg)
     S_prev = env.get_state()
     stats = U.FrameStats()
-    skipped = rounding = checked = n_done = 0
+    skipped = checked = n_done = 0
     errors = []
     for t in range(T):
         env.step(act_d[t], one, r1, d1)
@@ -286,26 +294,19 @@ def test_headline_fused_rollout_full_size():
                                            acts[t, i], g_after, r_np[i], d_np[i], S["events"][i])
             if skip:
                 skipped += 1
-                continue
             errors += [f"step {t} env {i}: {e}" for e in errs]
-            if errs:
-                continue
             n_done += int(d_np[i])
-            o32 = U.round32(o)
-            if not U.same_pose(g_after, o32):
-                rounding += 1
-                continue
-            oo, cols = orc.render(grids[i], oc, orc.state_from(o32))
-            U.compare_frame(stats, U.frame_of(one_np, env.obs_offsets, i, H, W_), oo, cols,
-                            tag=f"step {t} env {i}")
+            # the frame of the post-step state the GPU stored, rendered by both
+            U.check_frame(stats, U.frame_of(one_np, env.obs_offsets, i, H, W_), grids[i], oc,
+                          orc.state_from(g_after), tag=f"step {t} env {i}")
         S_prev = S
     assert np.array_equal(env.get_state_bytes(), fused_state), "final state differs"
     assert not errors, errors[:10]
     assert skipped <= max(2, checked // 50), f"too many flagged steps: {skipped}"
-    assert rounding <= max(3, checked // 10), f"poses one rounding apart: {rounding}"
+    stats.report(f"fused-rollout/{wl['name']}")
     assert not stats.mismatch, stats.mismatch[:10]
     assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
-    assert stats.cols >= 0.8 * checked * W_
+    assert stats.cols == checked * W_
     env.close()
 
 
@@ -368,21 +369,17 @@ def test_trajectory_tiny_full(wl):
                 continue
             assert drift < 1e-3, f"step {t} env {i}: drift {drift}"
             ost[i] = nxt
-            oo, cols = orc.render(grids[i], oc, nxt)
             g = obs_np[t].reshape(n, cfg["obs_h"], cfg["obs_w"], 3)[i]
             if d:
                 # episode starts are exact states: the frame must match outright
-                U.compare_frame(stats, g, oo, cols, tag=f"t{t} e{i}")
+                U.check_frame(stats, g, grids[i], oc, nxt, tag=f"t{t} e{i}")
                 exact_frames += 1
             else:
                 loose = U.FrameStats()
-                U.compare_frame(loose, g, oo, cols, tag=f"t{t} e{i}")
-                stats.cols += loose.cols
-                stats.flagged += loose.flagged
-                stats.f1 += loose.f1
+                U.check_frame(loose, g, grids[i], oc, nxt, tag=f"t{t} e{i}")
                 # states differ by the drift here: allow a column within the drift of a tie
-                if loose.mismatch:
-                    stats.mismatch += [m + " (drift)" for m in loose.mismatch]
+                loose.mismatch = [m + " (drift)" for m in loose.mismatch]
+                stats.add(loose)
     n_cols = stats.cols
     drift_mismatch = [m for m in stats.mismatch if m.endswith("(drift)")]
     hard = [m for m in stats.mismatch if not m.endswith("(drift)")]

@@ -99,6 +99,18 @@ ASCII_TINY = dict(number=7, name="ascii-16env-10x10-64px", n_envs=16, steps=400,
                               obs_h=64, obs_w=64))
 
 
+# Long rays: a 64x64 room walled only at its border (rays cross up to ~90
+# tiles), and the 64-side maze with every separator wall removed (a hall of
+# pillars, long rays between them).
+ROOM64 = "\n".join(["#" * 64] + ["#" + "." * 62 + "#"] * 62 + ["#" * 64])
+OPEN64 = dict(number=8, name="open-32env-64x64room-128px", n_envs=32,
+              cfg=env_cfg(side=64, ascii_map=ROOM64, goal_sprite=1, n_actions=6, episode_cap=256,
+                          obs_h=128, obs_w=128))
+PILLARS64 = dict(number=9, name="pillars-32env-64side-128px", n_envs=32,
+                 cfg=env_cfg(side=64, loop_frac=1.0, goal_sprite=1, n_actions=6, episode_cap=256,
+                             obs_h=128, obs_w=128))
+
+
 def seeds(number: int, n: int, offset: int = 0) -> np.ndarray:
     """seeds[i] = (number << 32) | (offset + i), as uint64."""
     i = np.arange(offset, offset + n, dtype=np.uint64)
