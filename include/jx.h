@@ -230,6 +230,26 @@ jx_status jx_rollout(jx_ctx* ctx, int32_t T, const uint8_t* actions_dev, uint8_t
                      int64_t obs_stride, float* reward_dev, uint8_t* done_dev,
                      uint8_t* prev_action_dev, int32_t flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same T
+ * steps as jx_rollout(ctx, T, ..., flags), with the same arguments, buffers
+ * and results bit for bit, under the context's launch mapping.  The persistent
+ * form's work-queue counters live in a static device array of the library
+ * (16 KiB, one copy per device, resolved by jx_create and held until the
+ * process ends) instead of the context's workspace; no input size can exceed
+ * it, since a launch uses at most 32 queues whatever the batch.  The call
+ * allocates nothing (no hipMalloc, hipFree, graph or host buffer) and only
+ * enqueues kernels on the context's stream: a kernel first clears the counters
+ * the previous call left in the array, so a captured call replays correctly.
+ * flags: 0 (T launches) or JX_ROLLOUT_FUSED (one launch); JX_ROLLOUT_GRAPH is
+ * rejected with JX_EINVAL (instantiating a graph allocates).  Every call on a
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, threads or contexts) race and must be serialised by the caller.
+ * JX_EDEVICE if the array could not be resolved when the context was created. */
+jx_status jx_rollout_noalloc(jx_ctx* ctx, int32_t T, const uint8_t* actions_dev, uint8_t* obs_dev,
+                             int64_t obs_stride, float* reward_dev, uint8_t* done_dev,
+                             uint8_t* prev_action_dev, int32_t flags);
+
 /* Renders the current state without stepping: one ray per image column to
  * the first blocking tile by DDA over tile boundaries, perpendicular distance,
  * column fill by hit tile and side (Sec. 2.1), billboard sprites (Fig. 1

@@ -42,6 +42,9 @@ struct jx_ctx {
   int n_cu = 1;
   LaunchCfg launch{0, 1, 4, 0};
   uint32_t seq = 0;  // persistent launches enqueued on this context's stream
+  // static scratch of jx_rollout_noalloc on this device (looked up at create)
+  uint32_t* scratch = nullptr;
+  int scratch_err = 0;
   // captured rollouts, keyed by (T, launch mapping)
   std::map<std::array<int32_t, 5>, hipGraphExec_t> graphs;
 };
@@ -357,6 +360,9 @@ jx_status jx_create(jx_ctx** out, int32_t device, void* hip_stream, void* worksp
   c->ws = (uint8_t*)workspace_dev;
   c->ws_bytes = ws_bytes;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  // the device is current: resolve this device's copy of the static scratch
+  // array once, here, so the entry point that allocates nothing needs no set-up
+  c->scratch_err = scratch_device_address(device, &c->scratch);
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return set_error(JX_EDEVICE, "stream creation failed");
@@ -474,8 +480,11 @@ jx_status jx_step(jx_ctx* c, const uint8_t* actions, uint8_t* obs, float* reward
   return launch_or_fail(c, io, c->stream);
 }
 
-jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs, int64_t obs_stride,
-                     float* reward, uint8_t* done, uint8_t* prev_action, int32_t flags) {
+// Arguments of a T-step rollout.  JX_OK with *nothing = true when there is no
+// work (no envs or T = 0).
+static jx_status check_rollout(const jx_ctx* c, int32_t T, const uint8_t* actions, const uint8_t* obs,
+                               int64_t obs_stride, const float* reward, const uint8_t* done, bool* nothing) {
+  *nothing = true;
   jx_status st = check_ready(c);
   if (st) return st;
   if (T < 0) return set_error(JX_EINVAL, "T < 0");
@@ -487,26 +496,45 @@ jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs,
       ((uintptr_t)obs & (al - 1)))
     return set_error(JX_EINVAL, "obs_stride must be 0 or >= jx_obs_bytes(); obs and obs_stride 4-byte aligned "
                                 "(16-byte for the floating formats)");
+  *nothing = false;
+  return JX_OK;
+}
+
+// The fused form: one launch for all T steps.
+static jx_status rollout_fused(jx_ctx* c, const DevState& S, int32_t T, const uint8_t* actions, uint8_t* obs,
+                               int64_t obs_stride, float* reward, uint8_t* done, uint8_t* prev_action) {
+  LaunchCfg lc = c->launch;
+  if (lc.form != JX_FORM_PLAIN || lc.waves_per_group > 8) lc = LaunchCfg{0, 4, 1, lc.store_mode};
+  int rc = launch_rollout_fused(S, actions, obs, obs_stride, reward, done, prev_action, T, lc, c->max_side,
+                                c->n_cu, c->stream);
+  if (rc) return set_error(JX_EDEVICE, std::string("fused rollout launch: ") + kernel_error_string(rc));
+  return JX_OK;
+}
+
+// Step t's I/O of a rollout whose buffers are given by value.
+static DevIo step_io(const jx_ctx* c, int t, const uint8_t* actions, uint8_t* obs, int64_t obs_stride,
+                     float* reward, uint8_t* done, uint8_t* prev_action) {
+  DevIo io{};
+  io.act = actions + (int64_t)t * c->n;
+  io.obs = obs + (int64_t)t * obs_stride;
+  io.rew = reward + (int64_t)t * c->n;
+  io.done = done + (int64_t)t * c->n;
+  io.prev = prev_action ? prev_action + (int64_t)t * c->n : nullptr;
+  io.mode = MODE_STEP;
+  io.store_mode = c->launch.store_mode;
+  return io;
+}
+
+jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs, int64_t obs_stride,
+                     float* reward, uint8_t* done, uint8_t* prev_action, int32_t flags) {
+  bool nothing = true;
+  jx_status st = check_rollout(c, T, actions, obs, obs_stride, reward, done, &nothing);
+  if (st || nothing) return st;
   HIPCHK(hipSetDevice(c->device));
-  if (flags & JX_ROLLOUT_FUSED) {
-    LaunchCfg lc = c->launch;
-    if (lc.form != JX_FORM_PLAIN || lc.waves_per_group > 8) lc = LaunchCfg{0, 4, 1, lc.store_mode};
-    int rc = launch_rollout_fused(c->S, actions, obs, obs_stride, reward, done, prev_action, T, lc,
-                                  c->max_side, c->n_cu, c->stream);
-    if (rc) return set_error(JX_EDEVICE, std::string("fused rollout launch: ") + kernel_error_string(rc));
-    return JX_OK;
-  }
+  if (flags & JX_ROLLOUT_FUSED) return rollout_fused(c, c->S, T, actions, obs, obs_stride, reward, done, prev_action);
   if (!(flags & JX_ROLLOUT_GRAPH)) {
     for (int t = 0; t < T; ++t) {
-      DevIo io{};
-      io.act = actions + (int64_t)t * c->n;
-      io.obs = obs + (int64_t)t * obs_stride;
-      io.rew = reward + (int64_t)t * c->n;
-      io.done = done + (int64_t)t * c->n;
-      io.prev = prev_action ? prev_action + (int64_t)t * c->n : nullptr;
-      io.mode = MODE_STEP;
-      io.store_mode = c->launch.store_mode;
-      st = launch_or_fail(c, io, c->stream);
+      st = launch_or_fail(c, step_io(c, t, actions, obs, obs_stride, reward, done, prev_action), c->stream);
       if (st) return st;
     }
     return JX_OK;
@@ -549,6 +577,38 @@ jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs,
   HIPCHK(hipGraphLaunch(it->second, c->stream));
   // the replay's last launch cleared counter set T % 4: continue from there
   if (c->launch.form == JX_FORM_PERSISTENT) c->seq = (uint32_t)T;
+  return JX_OK;
+}
+
+jx_status jx_rollout_noalloc(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs, int64_t obs_stride,
+                             float* reward, uint8_t* done, uint8_t* prev_action, int32_t flags) {
+  bool nothing = true;
+  jx_status st = check_rollout(c, T, actions, obs, obs_stride, reward, done, &nothing);
+  if (st) return st;
+  if (flags & ~JX_ROLLOUT_FUSED)
+    return set_error(JX_EINVAL, flags & JX_ROLLOUT_GRAPH
+                                    ? "JX_ROLLOUT_GRAPH is not accepted: instantiating a graph allocates (use jx_rollout)"
+                                    : "unknown rollout flags");
+  if (nothing) return JX_OK;
+  if (!c->scratch)
+    return set_error(JX_EDEVICE, std::string("static scratch of this device unavailable: ") +
+                                     kernel_error_string(c->scratch_err));
+  HIPCHK(hipSetDevice(c->device));
+  // the work-queue counters live in this device's static scratch array; every
+  // other field is the context's own
+  DevState S = c->S;
+  S.queues = c->scratch;
+  if (flags & JX_ROLLOUT_FUSED) return rollout_fused(c, S, T, actions, obs, obs_stride, reward, done, prev_action);
+  const bool queues = c->launch.form == JX_FORM_PERSISTENT && c->S.obs_fmt == 0;
+  // the last call on this device left its counts behind: clear every counter
+  // set with a kernel (capture-safe), then number the launches from 0
+  if (queues && launch_clear_queues(c->scratch, c->stream) != 0)
+    return set_error(JX_EDEVICE, "queue clear launch failed");
+  for (int t = 0; t < T; ++t) {
+    const DevIo io = step_io(c, t, actions, obs, obs_stride, reward, done, prev_action);
+    const int rc = launch_batch(S, io, nullptr, 0, c->launch, c->max_side, c->n_cu, (uint32_t)t, c->stream);
+    if (rc != 0) return set_error(JX_EDEVICE, std::string("kernel launch: ") + kernel_error_string(rc));
+  }
   return JX_OK;
 }
 

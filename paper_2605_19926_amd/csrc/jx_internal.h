@@ -143,12 +143,21 @@ struct LaunchCfg {
 // set (seq + 1) % kQueueSlots for the launch after it.
 constexpr int kQueues = 32, kQueueSlots = 4, kQueueStride = 32;
 constexpr int kQueueWords = kQueues * kQueueSlots * kQueueStride;
+// Static device scratch of the rollout entry point that allocates nothing: one
+// full set of queue counters (16 KiB).  Every batch size fits it: a launch uses
+// at most kQueues queues whatever the number of envs.
+constexpr int kScratchWords = kQueueWords;
+static_assert(kScratchWords * 4 == 16384, "scratch size");
 
 // rd != nullptr: the I/O of step t is taken from the device descriptor rd.
 // seq: launch sequence number (persistent form).
 int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t,
                  const LaunchCfg& lc, int max_side, int n_cu, uint32_t seq, void* stream);
 int launch_clear_queues(uint32_t* queues, void* stream);
+// Device address of the static scratch array on `device`, looked up on the
+// first call for that device, which must be made with the device current.
+// 0 or a hipError_t code.
+int scratch_device_address(int device, uint32_t** out);
 // One launch for T steps of every env (actions for all steps given up front).
 int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride,
                          float* rew, uint8_t* dn, uint8_t* prev, int T, const LaunchCfg& lc, int max_side, int n_cu,

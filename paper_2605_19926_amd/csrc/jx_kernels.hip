@@ -22,6 +22,8 @@
 // HBM write of the frames and the vector ALU of the span expansion.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "jx_internal.h"
 
 namespace jx {
@@ -1629,5 +1631,31 @@ int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, in
 }
 
 const char* kernel_error_string(int code) { return hipGetErrorString((hipError_t)code); }
+
+// Work-queue counters of the rollout entry point that allocates nothing: a
+// file-scope device array, one copy per device, alive until the process ends.
+// In host code `scratch` names a host-side stand-in, not a device address: the
+// kernels receive the address looked up below, once per device.
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int scratch_device_address(int device, uint32_t** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    g_scratch_ptr[device] = static_cast<uint32_t*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return 0;
+}
 
 }  // namespace jx

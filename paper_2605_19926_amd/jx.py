@@ -93,6 +93,7 @@ _SIGS = {
     "jx_obs_offsets": (_i32, [_vp, _vp]),
     "jx_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "jx_rollout": (_i32, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32]),
+    "jx_rollout_noalloc": (_i32, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32]),
     "jx_render": (_i32, [_vp, _vp, _vp]),
     "jx_state_bytes": (_sz, [_vp]),
     "jx_state_layout": (_i32, [_vp, ctypes.POINTER(jx_field), _i32, ctypes.POINTER(_i32)]),
@@ -309,6 +310,26 @@ class Env:
                 _need("obs", obs, (T - 1) * obs_stride + self.obs_bytes, self.dev)
         check(lib().jx_rollout(self.ctx, T, _ptr(actions), _ptr(obs), obs_stride, _ptr(reward),
                                _ptr(done), _ptr(prev), flags))
+
+    def rollout_noalloc(self, actions, obs, reward, done, T: int, obs_stride: int = 0,
+                        fused: bool = False, prev=None, flags: int | None = None):
+        """jx_rollout_noalloc: the rollout of ``rollout(..., graph=False)`` with
+        its work-queue counters in the library's static device array (no
+        allocation); ``flags`` overrides the flags passed (for error tests)."""
+        if flags is None:
+            flags = JX_ROLLOUT_FUSED if fused else 0
+        if T > 0:
+            _need("actions", actions, T * self.n, self.dev)
+            _need("reward", reward, 4 * T * self.n, self.dev)
+            _need("done", done, T * self.n, self.dev)
+            if prev is not None:
+                _need("prev", prev, T * self.n, self.dev)
+            if obs_stride and obs_stride < self.obs_bytes:
+                raise JxError(JX_EINVAL, f"obs_stride {obs_stride} < frame bytes {self.obs_bytes}")
+            if obs is not None:
+                _need("obs", obs, (T - 1) * obs_stride + self.obs_bytes, self.dev)
+        check(lib().jx_rollout_noalloc(self.ctx, T, _ptr(actions), _ptr(obs), obs_stride, _ptr(reward),
+                                       _ptr(done), _ptr(prev), flags))
 
     def render(self, obs=None, debug=None):
         self._check_frame(obs)
