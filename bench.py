@@ -574,6 +574,8 @@ def main() -> int:
     if not args.no_forms:
         line["batching_form"] = batch_form(jx, torch, [
             {"form": 0, "waves_per_group": 4, "groups_per_cu": 1, "store_mode": 0, "fused": True},
+            {"form": 1, "waves_per_group": 4, "groups_per_cu": 2, "store_mode": 0, "fused": True},
+            {"form": 1, "waves_per_group": 8, "groups_per_cu": 1, "store_mode": 0, "fused": True},
             {"form": 0, "waves_per_group": 4, "groups_per_cu": 1, "store_mode": 0},
             {"form": 1, "waves_per_group": 2, "groups_per_cu": 4, "store_mode": 0},
             {"form": 2, "waves_per_group": 2, "groups_per_cu": 2, "store_mode": 0}])

@@ -221,10 +221,13 @@ jx_status jx_step(jx_ctx* ctx, const uint8_t* actions_dev, uint8_t* obs_dev, flo
 /* flags & JX_ROLLOUT_FUSED: one launch runs all T steps; each wave keeps its
  * env's state on chip between steps and writes it back after the last step.
  * Outputs (frames, rewards, dones, final state) equal T single-step launches
- * bit for bit.  Takes precedence over JX_ROLLOUT_GRAPH.  Uses the plain
- * mapping's waves_per_group (4 when another form is selected, and always 4
- * for the training-buffer formats, which also run every per-step launch in the
- * plain form). */
+ * bit for bit.  Takes precedence over JX_ROLLOUT_GRAPH.  Under the plain
+ * mapping, waves take envs by a static stride (waves_per_group waves per
+ * workgroup); under the persistent mapping, groups_per_cu workgroups per
+ * compute unit claim envs one at a time from device work queues, costliest
+ * first (uneven shapes); the pipelined mapping and the training-buffer formats
+ * run the static stride with 4 waves per workgroup (those formats also run
+ * every per-step launch in the plain form). */
 #define JX_ROLLOUT_FUSED 2
 jx_status jx_rollout(jx_ctx* ctx, int32_t T, const uint8_t* actions_dev, uint8_t* obs_dev,
                      int64_t obs_stride, float* reward_dev, uint8_t* done_dev,

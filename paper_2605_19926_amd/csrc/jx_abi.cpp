@@ -500,13 +500,17 @@ static jx_status check_rollout(const jx_ctx* c, int32_t T, const uint8_t* action
   return JX_OK;
 }
 
-// The fused form: one launch for all T steps.
+// The fused form: one launch for all T steps.  Under the persistent mapping
+// (byte frames) persistent waves claim envs from the queue counters of launch
+// `seq`; the pipelined mapping runs the plain fused kernel with 4 waves per
+// workgroup.
 static jx_status rollout_fused(jx_ctx* c, const DevState& S, int32_t T, const uint8_t* actions, uint8_t* obs,
-                               int64_t obs_stride, float* reward, uint8_t* done, uint8_t* prev_action) {
+                               int64_t obs_stride, float* reward, uint8_t* done, uint8_t* prev_action,
+                               uint32_t seq) {
   LaunchCfg lc = c->launch;
-  if (lc.form != JX_FORM_PLAIN || lc.waves_per_group > 8) lc = LaunchCfg{0, 4, 1, lc.store_mode};
+  if (lc.form == JX_FORM_PIPELINE) lc = LaunchCfg{0, 4, 1, lc.store_mode};
   int rc = launch_rollout_fused(S, actions, obs, obs_stride, reward, done, prev_action, T, lc, c->max_side,
-                                c->n_cu, c->stream);
+                                c->n_cu, seq, c->stream);
   if (rc) return set_error(JX_EDEVICE, std::string("fused rollout launch: ") + kernel_error_string(rc));
   return JX_OK;
 }
@@ -531,7 +535,11 @@ jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs,
   jx_status st = check_rollout(c, T, actions, obs, obs_stride, reward, done, &nothing);
   if (st || nothing) return st;
   HIPCHK(hipSetDevice(c->device));
-  if (flags & JX_ROLLOUT_FUSED) return rollout_fused(c, c->S, T, actions, obs, obs_stride, reward, done, prev_action);
+  if (flags & JX_ROLLOUT_FUSED) {
+    st = rollout_fused(c, c->S, T, actions, obs, obs_stride, reward, done, prev_action, c->seq);
+    if (st == JX_OK && c->launch.form == JX_FORM_PERSISTENT) c->seq += 1;
+    return st;
+  }
   if (!(flags & JX_ROLLOUT_GRAPH)) {
     for (int t = 0; t < T; ++t) {
       st = launch_or_fail(c, step_io(c, t, actions, obs, obs_stride, reward, done, prev_action), c->stream);
@@ -598,12 +606,12 @@ jx_status jx_rollout_noalloc(jx_ctx* c, int32_t T, const uint8_t* actions, uint8
   // other field is the context's own
   DevState S = c->S;
   S.queues = c->scratch;
-  if (flags & JX_ROLLOUT_FUSED) return rollout_fused(c, S, T, actions, obs, obs_stride, reward, done, prev_action);
   const bool queues = c->launch.form == JX_FORM_PERSISTENT && c->S.obs_fmt == 0;
   // the last call on this device left its counts behind: clear every counter
   // set with a kernel (capture-safe), then number the launches from 0
   if (queues && launch_clear_queues(c->scratch, c->stream) != 0)
     return set_error(JX_EDEVICE, "queue clear launch failed");
+  if (flags & JX_ROLLOUT_FUSED) return rollout_fused(c, S, T, actions, obs, obs_stride, reward, done, prev_action, 0);
   for (int t = 0; t < T; ++t) {
     const DevIo io = step_io(c, t, actions, obs, obs_stride, reward, done, prev_action);
     const int rc = launch_batch(S, io, nullptr, 0, c->launch, c->max_side, c->n_cu, (uint32_t)t, c->stream);

@@ -159,9 +159,12 @@ int launch_clear_queues(uint32_t* queues, void* stream);
 // 0 or a hipError_t code.
 int scratch_device_address(int device, uint32_t** out);
 // One launch for T steps of every env (actions for all steps given up front).
+// lc.form 1 (persistent, byte frames): persistent waves claim envs from the
+// queue counters of launch `seq`, as launch_batch does; otherwise a static
+// stride of lc.waves_per_group-wave workgroups.
 int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride,
                          float* rew, uint8_t* dn, uint8_t* prev, int T, const LaunchCfg& lc, int max_side, int n_cu,
-                         void* stream);
+                         uint32_t seq, void* stream);
 int launch_set_desc(RolloutDesc* rd_dev, const RolloutDesc& value, void* stream);
 int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeItem* items_dev,
                  int n_items, uint32_t* queues_dev, uint32_t seq, int waves_per_group,

@@ -1205,7 +1205,7 @@ struct QueueView {
 
 template <int WPB>
 __device__ __forceinline__ QueueView queue_view(uint32_t* queues, uint32_t seq, int n_items, int w,
-                                                int lane) {
+                                                int lane, int max_chunk = 1 << 30) {
   QueueView v;
   const int grid = (int)gridDim.x;
   v.nq = grid < kQueues ? grid : kQueues;
@@ -1216,7 +1216,7 @@ __device__ __forceinline__ QueueView queue_view(uint32_t* queues, uint32_t seq, 
   v.waves = ((grid - v.q + v.nq - 1) / v.nq) * WPB;
   v.wave = ((int)blockIdx.x / v.nq) * WPB + w;
   const int c = v.items / (2 * v.waves);
-  v.chunk = c < 1 ? 1 : c;
+  v.chunk = c < 1 ? 1 : (c > max_chunk ? max_chunk : c);
   if (blockIdx.x == 0 && w == 0 && lane < kQueues) {
     const int nxt = (int)((seq + 1) % kQueueSlots);
     queues[(nxt * kQueues + lane) * kQueueStride] = 0u;
@@ -1333,14 +1333,95 @@ __global__ __launch_bounds__(128 * P) void k_pipe(DevState S, DevIo io0, const R
   }
 }
 
-// Fused rollout: each wave carries its env through all T steps of a rollout
-// with the state in registers and its layout staged once in LDS, loading the
-// env's actions 128 steps at a time.  Inside the
-// step loop the wave issues no global loads, so its frame stores never stall
-// it, and waves drift out of phase: one wave's casting overlaps another's
-// stores.  Waves take envs by a static stride over the work order.  Per step
-// the results are those of a single-step launch; the state is written back
-// once, after the last step.
+// One env's fused rollout: the wave carries the env through all T steps with
+// the state in registers and its layout staged once in LDS, loading the env's
+// actions 128 steps at a time.  Inside the step loop the wave issues no global
+// loads, so its frame stores never stall it, and waves drift out of phase: one
+// wave's casting overlaps another's stores.  Per step the results are those of
+// a single-step launch; the state is written back once, after the last step.
+template <int MAXN, bool ASC, int FMT>
+__device__ __forceinline__ void roll_env(const DevState& S, int env, int lane, uint8_t* lmap, const uint32_t* lclr,
+                                         const uint32_t* lcvt, uint32_t* lcol, const uint8_t* act, uint8_t* obs,
+                                         int64_t obs_stride, float* rew, uint8_t* dn, uint8_t* prv, int T,
+                                         int store_mode, const DevIo& io) {
+  const int64_t n = S.n;
+  EnvIn<MAXN> in;
+  load_env<MAXN>(S, env, lane, in);
+  stage_map<MAXN>(in, lane, lmap);
+  const int64_t obs_off = obs_off_of(S, env);
+  uint32_t n_invalid = 0, last_ev = 0;
+  for (int t0 = 0; t0 < T; t0 += 128) {
+    // lane l holds the actions of steps t0 + l and t0 + 64 + l
+    const int s0 = t0 + lane, s1 = t0 + 64 + lane;
+    const uint32_t a0 = s0 < T ? act[(int64_t)s0 * n + env] : 0u;
+    const uint32_t a1 = s1 < T ? act[(int64_t)s1 * n + env] : 0u;
+    const int tend = T - t0 < 128 ? T - t0 : 128;
+    for (int k = 0; k < tend; ++k) {
+      // (& 0xFF: the action is a byte, so produce_env's load path for a
+      // negative action folds away and the step loop issues no load)
+      // Wait for this wave's previous frame stores before the next step: a
+      // wave then has at most one frame's stores in flight.  Measured on the
+      // 4096-env workload this bound keeps the HBM write stream more
+      // efficient than letting stores of many steps pile up (and the casting
+      // of the other waves still overlaps them).  vmcnt 0, other counters
+      // untouched.
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      const int a = __shfl((int)(k < 64 ? a0 : a1), k & 63, 64) & 0xFF;
+      // an opaque copy of the lane id keeps the per-column set-up inside the
+      // loop instead of hoisted out of it and held live across all steps
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
+      EnvOut o;
+      produce_env<MAXN, false, ASC>(in, S, io, a, ln, lmap, lclr, lcol, o);
+      const int t = t0 + k;
+      fill_frame<FMT>(lcol, lcvt, obs + (int64_t)t * obs_stride + obs_off, o.W, o.H, ln, store_mode);
+      if (lane == 0) {
+        rew[(int64_t)t * n + env] = o.reward;
+        dn[(int64_t)t * n + env] = (uint8_t)o.done;
+        if (prv) prv[(int64_t)t * n + env] = (uint8_t)o.prev;
+      }
+      // the carried state is uniform across the wave: keep it in scalar registers
+      const uint32_t ev = uniform_u(o.ev);
+      n_invalid += (ev & EV_INVALID) ? 1u : 0u;
+      last_ev = ev;
+      in.x = uniform_f(o.x);
+      in.y = uniform_f(o.y);
+      in.th = uniform_f(o.th);
+      in.t = uniform_u(o.t);
+      in.ep = uniform_u(o.ep);
+      in.fl = uniform_u(o.fl);
+      in.nd = (int)uniform_u(o.nd);
+      in.goal = (int)uniform_u((uint32_t)o.goal);
+      in.door = (int)uniform_u((uint32_t)o.door);
+      in.key = (int)uniform_u((uint32_t)o.key);
+      in.dec0 = (int)uniform_u((uint32_t)o.dec0);
+      in.dec1 = (int)uniform_u((uint32_t)o.dec1);
+      in.doors = uniform_u(o.doors);
+      in.sn = uniform_d(o.sn);
+      in.cs = uniform_d(o.cs);
+    }
+  }
+  if (lane == 0 && T > 0) {
+    S.x[env] = in.x;
+    S.y[env] = in.y;
+    S.th[env] = in.th;
+    S.t[env] = in.t;
+    S.ep[env] = in.ep;
+    S.goal[env] = in.goal;
+    S.door[env] = in.door;
+    S.key[env] = in.key;
+    S.decor[2 * env] = in.dec0;
+    S.decor[2 * env + 1] = in.dec1;
+    S.flags[env] = (uint8_t)in.fl;
+    S.ndecor[env] = (uint8_t)in.nd;
+    S.events[env] = (uint8_t)last_ev;
+    S.doors[env] = in.doors;
+    if (n_invalid) S.invalid[env] += n_invalid;
+  }
+}
+
+// Fused rollout: one launch for T steps of every env.  Waves take envs by a
+// static stride over the work order (costliest first).
 template <int MAXN, int WPB, bool ASC, int FMT>
 __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* act, uint8_t* obs,
                                                    int64_t obs_stride, float* rew, uint8_t* dn,
@@ -1352,87 +1433,43 @@ __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* ac
   stage_tables<FMT>(sclr, scvt);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int waves = (int)gridDim.x * WPB;
-  const int64_t n = S.n;
   DevIo io{};
   io.obs = obs;
   io.mode = MODE_STEP;
   io.store_mode = store_mode;
   for (int item = (int)blockIdx.x * WPB + w; item < S.n; item += waves) {
     const int env = __builtin_amdgcn_readfirstlane(S.order[item]);
-    EnvIn<MAXN> in;
-    load_env<MAXN>(S, env, lane, in);
-    stage_map<MAXN>(in, lane, smap[w]);
-    const int64_t obs_off = obs_off_of(S, env);
-    uint32_t n_invalid = 0, last_ev = 0;
-    for (int t0 = 0; t0 < T; t0 += 128) {
-      // lane l holds the actions of steps t0 + l and t0 + 64 + l
-      const int s0 = t0 + lane, s1 = t0 + 64 + lane;
-      const uint32_t a0 = s0 < T ? act[(int64_t)s0 * n + env] : 0u;
-      const uint32_t a1 = s1 < T ? act[(int64_t)s1 * n + env] : 0u;
-      const int tend = T - t0 < 128 ? T - t0 : 128;
-      for (int k = 0; k < tend; ++k) {
-        // (& 0xFF: the action is a byte, so produce_env's load path for a
-        // negative action folds away and the step loop issues no load)
-        // Wait for this wave's previous frame stores before the next step: a
-        // wave then has at most one frame's stores in flight.  Measured on the
-        // 4096-env workload this bound keeps the HBM write stream more
-        // efficient than letting stores of many steps pile up (and the casting
-        // of the other waves still overlaps them).  vmcnt 0, other counters
-        // untouched.
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        const int a = __shfl((int)(k < 64 ? a0 : a1), k & 63, 64) & 0xFF;
-        // an opaque copy of the lane id keeps the per-column set-up inside the
-        // loop instead of hoisted out of it and held live across all steps
-        int ln = lane;
-        asm volatile("" : "+v"(ln));
-        EnvOut o;
-        produce_env<MAXN, false, ASC>(in, S, io, a, ln, smap[w], sclr, scol[w], o);
-        const int t = t0 + k;
-        fill_frame<FMT>(scol[w], scvt, obs + (int64_t)t * obs_stride + obs_off, o.W, o.H, ln, store_mode);
-        if (lane == 0) {
-          rew[(int64_t)t * n + env] = o.reward;
-          dn[(int64_t)t * n + env] = (uint8_t)o.done;
-          if (prv) prv[(int64_t)t * n + env] = (uint8_t)o.prev;
-        }
-        // the carried state is uniform across the wave: keep it in scalar registers
-        const uint32_t ev = uniform_u(o.ev);
-        n_invalid += (ev & EV_INVALID) ? 1u : 0u;
-        last_ev = ev;
-        in.x = uniform_f(o.x);
-        in.y = uniform_f(o.y);
-        in.th = uniform_f(o.th);
-        in.t = uniform_u(o.t);
-        in.ep = uniform_u(o.ep);
-        in.fl = uniform_u(o.fl);
-        in.nd = (int)uniform_u(o.nd);
-        in.goal = (int)uniform_u((uint32_t)o.goal);
-        in.door = (int)uniform_u((uint32_t)o.door);
-        in.key = (int)uniform_u((uint32_t)o.key);
-        in.dec0 = (int)uniform_u((uint32_t)o.dec0);
-        in.dec1 = (int)uniform_u((uint32_t)o.dec1);
-        in.doors = uniform_u(o.doors);
-        in.sn = uniform_d(o.sn);
-        in.cs = uniform_d(o.cs);
-      }
-    }
-    if (lane == 0 && T > 0) {
-      S.x[env] = in.x;
-      S.y[env] = in.y;
-      S.th[env] = in.th;
-      S.t[env] = in.t;
-      S.ep[env] = in.ep;
-      S.goal[env] = in.goal;
-      S.door[env] = in.door;
-      S.key[env] = in.key;
-      S.decor[2 * env] = in.dec0;
-      S.decor[2 * env + 1] = in.dec1;
-      S.flags[env] = (uint8_t)in.fl;
-      S.ndecor[env] = (uint8_t)in.nd;
-      S.events[env] = (uint8_t)last_ev;
-      S.doors[env] = in.doors;
-      if (n_invalid) S.invalid[env] += n_invalid;
-    }
+    roll_env<MAXN, ASC, FMT>(S, env, lane, smap[w], sclr, scvt, scol[w], act, obs, obs_stride, rew, dn, prv, T,
+                             store_mode, io);
   }
+}
+
+// Persistent fused rollout: a grid sized to the chip's resident waves drains
+// the work order (costliest first) one env per claim, each env carried
+// through all T steps as in k_roll.  An env of a 128 x 128 frame costs 16
+// times one of 32 x 32, so with uneven shapes dynamic claims keep every wave
+// busy until the queue is empty (longest-first list scheduling) where a
+// static stride leaves workgroups waiting on their slowest wave.  The queues
+// and counter sets are those of k_persist (one claim per env: chunk 1).
+template <int MAXN, int WPB, bool ASC>
+__global__ __launch_bounds__(64 * WPB) void k_proll(DevState S, const uint8_t* act, uint8_t* obs,
+                                                    int64_t obs_stride, float* rew, uint8_t* dn,
+                                                    uint8_t* prv, int T, int store_mode, uint32_t seq) {
+  __shared__ __align__(16) uint8_t smap[WPB][MAXN * MAXN];
+  __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
+  __shared__ uint32_t sclr[kColorWords];
+  stage_colors(sclr);
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  DevIo io{};
+  io.obs = obs;
+  io.mode = MODE_STEP;
+  io.store_mode = store_mode;
+  const QueueView v = queue_view<WPB>(S.queues, seq, S.n, w, lane, 1);
+  queue_drain(v, lane, [&](int pos) {
+    const int env = __builtin_amdgcn_readfirstlane(S.order[pos]);
+    roll_env<MAXN, ASC, 0>(S, env, lane, smap[w], sclr, nullptr, scol[w], act, obs, obs_stride, rew, dn, prv, T,
+                           store_mode, io);
+  });
 }
 
 __global__ void k_clear_queues(uint32_t* q) {
@@ -1506,6 +1543,19 @@ int launch_roll_n(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t o
   }
 }
 
+template <int MAXN, bool ASC, int FMT>
+int launch_proll_n(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride, float* rew,
+                   uint8_t* dn, uint8_t* pv, int T, int wpb, int groups, int nt, uint32_t seq, hipStream_t st) {
+  switch (wpb) {
+    case 1: hipLaunchKernelGGL((k_proll<MAXN, 1, ASC>), dim3(groups), dim3(64), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt, seq); break;
+    case 2: hipLaunchKernelGGL((k_proll<MAXN, 2, ASC>), dim3(groups), dim3(128), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt, seq); break;
+    case 4: hipLaunchKernelGGL((k_proll<MAXN, 4, ASC>), dim3(groups), dim3(256), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt, seq); break;
+    case 8: hipLaunchKernelGGL((k_proll<MAXN, 8, ASC>), dim3(groups), dim3(512), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt, seq); break;
+    default: return -1;
+  }
+  return (int)hipGetLastError();
+}
+
 template <bool ASC>
 int launch_persist_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb,
                      int groups, uint32_t seq, hipStream_t st) {
@@ -1566,6 +1616,14 @@ struct RollL {
   }
 };
 
+template <int MAXN, bool ASC, int FMT>
+struct PRollL {
+  static int run(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride, float* rew,
+                 uint8_t* dn, uint8_t* pv, int T, int wpb, int groups, int nt, uint32_t seq, hipStream_t st) {
+    return launch_proll_n<MAXN, ASC, FMT>(s, act, obs, obs_stride, rew, dn, pv, T, wpb, groups, nt, seq, st);
+  }
+};
+
 int launch_set_desc(RolloutDesc* rd_dev, const RolloutDesc& value, void* stream) {
   hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), rd_dev,
                      value);
@@ -1619,9 +1677,19 @@ int launch_serve(const DevState* states_dev, const DevIo* ios_dev, const ServeIt
 
 int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride,
                          float* rew, uint8_t* dn, uint8_t* prev, int T, const LaunchCfg& lc, int max_side,
-                         int n_cu, void* stream) {
+                         int n_cu, uint32_t seq, void* stream) {
   if (s.n <= 0 || T <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (lc.form == 1 && s.obs_fmt == 0) {
+    // persistent: the chip's share of resident workgroups, never more than needed
+    const int wpb = lc.waves_per_group;
+    int groups = n_cu * lc.groups_per_cu;
+    const int need = (s.n + wpb - 1) / wpb;
+    if (groups > need) groups = need;
+    if (groups < 1) groups = 1;
+    return by_shape_f<PRollL, 0>(s, max_side, act, obs, obs_stride, rew, dn, prev, T, wpb, groups, lc.store_mode,
+                                 seq, st);
+  }
   const int wpb = s.obs_fmt != 0 ? kFmtWaves : lc.waves_per_group;
   // one wave per env while they fit on the chip (16 waves per CU), else a stride
   int groups = (s.n + wpb - 1) / wpb;

@@ -71,7 +71,11 @@ def test_graph_eager_persistent_identical():
                 ("eager", dict(form=2, waves_per_group=2, groups_per_cu=2, store_mode=1)),
                 ("graph", dict(form=2, waves_per_group=4, groups_per_cu=4, store_mode=0)),
                 ("fused", dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0)),
-                ("fused", dict(form=0, waves_per_group=1, groups_per_cu=1, store_mode=1))]
+                ("fused", dict(form=0, waves_per_group=1, groups_per_cu=1, store_mode=1)),
+                # persistent fused rollouts: envs claimed one at a time
+                ("fused", dict(form=1, waves_per_group=4, groups_per_cu=2, store_mode=0)),
+                ("fused", dict(form=1, waves_per_group=1, groups_per_cu=1, store_mode=1)),
+                ("fused", dict(form=1, waves_per_group=8, groups_per_cu=1, store_mode=0))]
     _forms_equal(cfg, seeds, None, 40, launches)
 
 
@@ -87,7 +91,8 @@ def test_ascii_maps_every_form_identical():
                 ("graph", dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0)),
                 ("graph", dict(form=1, waves_per_group=2, groups_per_cu=4, store_mode=0)),
                 ("graph", dict(form=2, waves_per_group=2, groups_per_cu=2, store_mode=1)),
-                ("fused", dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0))]
+                ("fused", dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0)),
+                ("fused", dict(form=1, waves_per_group=2, groups_per_cu=3, store_mode=0))]
     ref = _forms_equal(cfgs, seeds, idx, 150, launches)
     # doors were opened and keys taken along the way
     assert ref[1].max() >= 0.5
@@ -100,6 +105,8 @@ def test_fused_rollout_long_and_resets():
     seeds = W.seeds(12, 300)
     _forms_equal(cfg, seeds, None, 200, [("eager", PLAIN1),
                                          ("fused", dict(form=0, waves_per_group=8, groups_per_cu=1,
+                                                        store_mode=0)),
+                                         ("fused", dict(form=1, waves_per_group=4, groups_per_cu=1,
                                                         store_mode=0))])
 
 
@@ -158,7 +165,9 @@ def test_mixed_shapes_batch_identical_and_oracle():
                 ("graph", dict(form=1, waves_per_group=1, groups_per_cu=8, store_mode=1)),
                 ("graph", dict(form=2, waves_per_group=2, groups_per_cu=1, store_mode=0)),
                 ("eager", dict(form=2, waves_per_group=4, groups_per_cu=2, store_mode=1)),
-                ("fused", dict(form=0, waves_per_group=2, groups_per_cu=1, store_mode=0))]
+                ("fused", dict(form=0, waves_per_group=2, groups_per_cu=1, store_mode=0)),
+                ("fused", dict(form=1, waves_per_group=4, groups_per_cu=2, store_mode=0)),
+                ("fused", dict(form=1, waves_per_group=2, groups_per_cu=16, store_mode=1))]
     _forms_equal(cfgs, seeds, idx, 12, launches)
     # oracle parity of the mixed batch from shared states (render + one step)
     env = U.env_of(cfgs, seeds, idx, obs=False)
