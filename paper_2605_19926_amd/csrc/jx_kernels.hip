@@ -758,42 +758,30 @@ __device__ void render_columns(const DevCfg& cf, const DevIo& io, int env, int l
 constexpr int kWaitTwoPairs = 0x0F74;
 
 // Expands the span records into the frame, one mirrored row pair per lane and
-// iteration: lane -> (column group cq, distance i from the horizon).
+// iteration: lane -> (column group cq, distance i from the horizon).  The
+// wave's di * Q lanes cover di row pairs of every column group per iteration
+// (Q = W / 4 groups, di = 64 / Q), so each lane's group is fixed.
 template <int FMT>
 __device__ void fill_frame_f(const uint32_t* lcol, const uint32_t* lcvt, uint8_t* base, int W, int H, int lane,
                              int nt) {
   using F = ObsFmt<FMT>;
-  const int Q = W >> 2, H2 = H >> 1, G2 = H2 * Q;
+  const int Q = W >> 2, H2 = H >> 1;
   const int64_t rowb = F::row_bytes(W), plane = (int64_t)H * W * F::kElem;
-  int i = lane / Q, cq = lane - i * Q;
-  const int di = 64 / Q, dq = 64 - di * Q;
-  if (dq == 0) {
-    if (lane < G2) {
-      const ColGroupF<FMT> g = col_group_f<FMT>(lcol, lcvt, cq);
-      uint8_t* up = base + (int64_t)(H2 - 1 - i) * rowb + F::kGroupBytes * cq;
-      uint8_t* dn = base + (int64_t)(H2 + i) * rowb + F::kGroupBytes * cq;
-      const int64_t step = (int64_t)di * rowb;
-      uint32_t ii = (uint32_t)i * kRowStep;
-      const uint32_t dii = (uint32_t)di * kRowStep;
-      for (; i < H2; i += di) {
-        emit_pair_f<FMT>(g, (uint32_t)i, ii, up, dn, plane, nt);
-        ii += dii;
-        up -= step;
-        dn += step;
-      }
-    }
-  } else {
-    for (int k = lane; k < G2; k += 64) {
-      const ColGroupF<FMT> g = col_group_f<FMT>(lcol, lcvt, cq);
-      emit_pair_f<FMT>(g, (uint32_t)i, (uint32_t)i * kRowStep,
-                       base + (int64_t)(H2 - 1 - i) * rowb + F::kGroupBytes * cq,
-                       base + (int64_t)(H2 + i) * rowb + F::kGroupBytes * cq, plane, nt);
-      i += di;
-      cq += dq;
-      if (cq >= Q) {
-        cq -= Q;
-        ++i;
-      }
+  const int di = 64 / Q;
+  int i = lane / Q;
+  const int cq = lane - i * Q;
+  if (lane < di * Q) {
+    const ColGroupF<FMT> g = col_group_f<FMT>(lcol, lcvt, cq);
+    uint8_t* up = base + (int64_t)(H2 - 1 - i) * rowb + F::kGroupBytes * cq;
+    uint8_t* dn = base + (int64_t)(H2 + i) * rowb + F::kGroupBytes * cq;
+    const int64_t step = (int64_t)di * rowb;
+    uint32_t ii = (uint32_t)i * kRowStep;
+    const uint32_t dii = (uint32_t)di * kRowStep;
+    for (; i < H2; i += di) {
+      emit_pair_f<FMT>(g, (uint32_t)i, ii, up, dn, plane, nt);
+      ii += dii;
+      up -= step;
+      dn += step;
     }
   }
 }
@@ -805,39 +793,28 @@ __device__ void fill_frame(const uint32_t* lcol, const uint32_t* lcvt, uint8_t* 
     fill_frame_f<FMT>(lcol, lcvt, base, W, H, lane, nt);
     return;
   }
-  const int Q = W >> 2, H2 = H >> 1, G2 = H2 * Q;
+  // lane -> (column group cq, first distance i); the wave's di * Q lanes
+  // (all 64 when Q divides 64, 63 of them at W = 84) cover di row pairs of
+  // every column group per iteration, so each lane's column group is fixed and
+  // its records stay in registers.
+  const int Q = W >> 2, H2 = H >> 1;
   const int rowb = 3 * W;
-  int i = lane / Q, cq = lane - i * Q;
-  const int di = 64 / Q, dq = 64 - di * Q;
-  if (dq == 0) {
-    // the lane's column group is fixed: keep its records in registers
-    if (lane < G2) {
-      const ColGroup g = col_group(lcol, cq);
-      uint8_t* up = base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq;
-      uint8_t* dn = base + (int64_t)(H2 + i) * rowb + 12 * cq;
-      const int64_t step = (int64_t)di * rowb;
-      uint32_t ii = (uint32_t)i * kRowStep;
-      const uint32_t dii = (uint32_t)di * kRowStep;
-      for (; i < H2; i += di) {
-        emit_pair(g, (uint32_t)i, ii, up, dn, nt);
-        __builtin_amdgcn_s_waitcnt(kWaitTwoPairs);
-        ii += dii;
-        up -= step;
-        dn += step;
-      }
-    }
-  } else {
-    for (int k = lane; k < G2; k += 64) {
-      const ColGroup g = col_group(lcol, cq);
-      emit_pair(g, (uint32_t)i, (uint32_t)i * kRowStep, base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq,
-                base + (int64_t)(H2 + i) * rowb + 12 * cq, nt);
+  const int di = 64 / Q;
+  int i = lane / Q;
+  const int cq = lane - i * Q;
+  if (lane < di * Q) {
+    const ColGroup g = col_group(lcol, cq);
+    uint8_t* up = base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq;
+    uint8_t* dn = base + (int64_t)(H2 + i) * rowb + 12 * cq;
+    const int64_t step = (int64_t)di * rowb;
+    uint32_t ii = (uint32_t)i * kRowStep;
+    const uint32_t dii = (uint32_t)di * kRowStep;
+    for (; i < H2; i += di) {
+      emit_pair(g, (uint32_t)i, ii, up, dn, nt);
       __builtin_amdgcn_s_waitcnt(kWaitTwoPairs);
-      i += di;
-      cq += dq;
-      if (cq >= Q) {
-        cq -= Q;
-        ++i;
-      }
+      ii += dii;
+      up -= step;
+      dn += step;
     }
   }
 }

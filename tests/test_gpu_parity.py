@@ -226,7 +226,10 @@ def test_one_step_keydoor_sampled():
 
 
 @pytest.mark.parametrize("side,hw", [(5, (2, 4)), (64, (128, 128)), (9, (84, 84)), (33, (32, 32)),
-                                     (64, (32, 128)), (16, (128, 4))])
+                                     (64, (32, 128)), (16, (128, 4)),
+                                     # widths whose column-group count does not divide
+                                     # the wave: 55 of 64 lanes at W = 44, 62 at W = 124
+                                     (12, (30, 44)), (24, (64, 124))])
 def test_one_step_shape_extremes(side, hw):
     cfg = W.env_cfg(side=side, loop_frac=0.1, key_door=1 if side >= 9 else 0, goal_sprite=1,
                     max_decor=2, obs_h=hw[0], obs_w=hw[1], episode_cap=64)
