@@ -217,18 +217,21 @@ def batch_form(jx, torch, launches: list[dict], rollouts: int = 2) -> dict:
 
 
 def serve_form(jx, n_requests: int, mode: int, rate: float = W.SERVE["rate"],
-               budget: int = int(64e9), n_streams: int = 4) -> dict:
+               budget: int = int(64e9), n_streams: int = 4, device_results: bool = False) -> dict:
     """Serving workload: Poisson arrivals over 256 client slots, clients of
     1-512 envs (log-uniform), side 8-64, frames 64 or 84 square.  Every client is
     opened before the clock starts (with a tight budget most of them queue for
     admission).  The library's native load generator (jx_server_replay) submits
     each request at its trace time, closes a client right after its last
     request, and collects completed requests in completion order from four
-    threads, copying their frames, rewards and dones to host memory.  Latency
-    is submit-to-ready as measured by the server."""
+    threads, copying their frames, rewards and dones to host memory (or, with
+    device_results, leaving them in each client's device rings of two slots,
+    as a learner on the same GPU would read them).  Latency is submit-to-ready
+    as measured by the server."""
     tr = W.serve_trace(n_requests, rate=rate)
     srv = jx.Server(hbm_budget=budget, n_streams=n_streams, mode=mode)
     sessions = {}
+    ring_keep = []   # device result rings, alive until the server is closed
     last_of = {}
     for k, sid in enumerate(tr["session"]):
         last_of[int(sid)] = k
@@ -241,7 +244,15 @@ def serve_form(jx, n_requests: int, mode: int, rate: float = W.SERVE["rate"],
             ob = int(tr["obs"][sid])
             cfg = W.env_cfg(side=side, loop_frac=0.1, goal_sprite=1, obs_h=ob, obs_w=ob)
             seeds = tr["seed_base"][sid] + np.arange(n, dtype=np.uint64)
-            cid, admitted = srv.open(seeds, cfg)
+            if device_results:
+                import torch
+                rings = (torch.empty(2 * n * ob * ob * 3, dtype=torch.uint8, device="cuda"),
+                         torch.empty(2 * n, dtype=torch.float32, device="cuda"),
+                         torch.empty(2 * n, dtype=torch.uint8, device="cuda"))
+                ring_keep.append(rings)
+                cid, admitted = srv.open_dev(seeds, cfg, *rings, slots=2)
+            else:
+                cid, admitted = srv.open(seeds, cfg)
             queued += 0 if admitted else 1
             sessions[sid] = (cid, n)
     # everything the replay needs is prepared before the clock
@@ -251,12 +262,14 @@ def serve_form(jx, n_requests: int, mode: int, rate: float = W.SERVE["rate"],
     close_after = np.array([last_of[int(s)] == k for k, s in enumerate(tr["session"])], np.uint8)
     lat, t_submitted, wall = srv.replay(tr["t"], cids, acts, close_after, n_collectors=4, timeout=600.0)
     progress(f"serving {'coalesced' if mode == jx.JX_SERVE_COALESCE else 'plain'} "
-             f"rate {rate:g}/s budget {budget} done")
+             f"rate {rate:g}/s budget {budget}{' device results' if device_results else ''} done")
     st = srv.stats()
     srv.close()
     lat_ms = lat * 1e3
     env_steps = int(sum(sessions[int(s)][1] for s in tr["session"]))
+    del ring_keep
     return {"mode": "coalesced" if mode == jx.JX_SERVE_COALESCE else "plain-per-request",
+            "results": "device rings" if device_results else "host copies",
             "driver": "native replay (jx_server_replay), 4 collector threads",
             "streams": n_streams if mode == jx.JX_SERVE_COALESCE else 1,
             "offered_req_per_s": rate, "submitted_req_per_s": n_requests / t_submitted,
@@ -591,7 +604,11 @@ def main() -> int:
                      serve_form(jx, nr, jx.JX_SERVE_PLAIN, rate=8 * W.SERVE["rate"]),
                      serve_form(jx, nr, jx.JX_SERVE_COALESCE, rate=16 * W.SERVE["rate"]),
                      serve_form(jx, nr, jx.JX_SERVE_PLAIN, rate=16 * W.SERVE["rate"]),
-                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, budget=24 << 20)]}
+                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, budget=24 << 20),
+                     # results left in device rings (no copy to the host)
+                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, device_results=True),
+                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, rate=16 * W.SERVE["rate"], device_results=True),
+                     serve_form(jx, nr, jx.JX_SERVE_COALESCE, rate=32 * W.SERVE["rate"], device_results=True)]}
         # the metric's second half: served step latency vs the plain per-request
         # launch at the serving workload's own arrival rate
         runs = line["serving_form"]["runs"]

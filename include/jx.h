@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define JX_ABI_VERSION 4
+#define JX_ABI_VERSION 5
 
 typedef int32_t jx_status;
 #define JX_OK 0
@@ -312,7 +312,10 @@ typedef struct jx_server jx_server;
 #define JX_SERVE_PLAIN 1     /* mode: one launch per request, FIFO, one stream */
 
 /* hbm_budget_bytes bounds the device memory of admitted clients' state and
- * maps.  Each stream also holds a 128 MiB device staging buffer for its
+ * maps.  Testing hook: when the environment variable JX_SERVER_FAIL_LAUNCH
+ * holds an integer k >= 0 at creation, the server's k-th launch (0-based, in
+ * issue order) is treated as failed without any HIP call being made for it, so
+ * the failure path below can be exercised with every kernel exiting normally.  Each stream also holds a 128 MiB device staging buffer for its
  * launches (descriptors, actions, results), and the server a pinned host arena
  * of min(budget, 2 GiB) mirroring it; one step of a client must fit both.
  * n_streams 1..8.  max_batch_envs bounds envs per launch (0 = no bound). */
@@ -328,15 +331,34 @@ void jx_server_destroy(jx_server* srv);
 jx_status jx_server_open(jx_server* srv, int32_t n_envs, const uint64_t* seeds_host,
                          const jx_env_cfg* cfg, int32_t* client);
 
+/* Opens a client whose results stay on the device (the step's consumer, such
+ * as a learner on the same GPU, reads them there; nothing is copied to the
+ * host): obs_dev [slots][n_envs][H][W][3] uint8, reward_dev [slots][n_envs]
+ * float32 and done_dev [slots][n_envs] uint8 are caller-owned device memory on
+ * the server's device (obs and reward 4-byte aligned) that must stay valid
+ * until the client's last request has been collected.  The client's requests
+ * run in submission order and the k-th of them (0-based) writes slot
+ * k mod slots, so a caller that keeps at most `slots` requests uncollected
+ * never has a slot overwritten before it has read it.  jx_server_wait on such a
+ * request takes no host buffers (JX_EINVAL otherwise).  Admission and errors as
+ * jx_server_open; JX_EINVAL for null rings or slots < 1. */
+jx_status jx_server_open_dev(jx_server* srv, int32_t n_envs, const uint64_t* seeds_host, const jx_env_cfg* cfg,
+                             uint8_t* obs_dev, float* reward_dev, uint8_t* done_dev, int32_t slots,
+                             int32_t* client);
+
 /* Queues one step of `client` with actions_host[n_envs] (copied).  *ticket
- * identifies the request. */
+ * identifies the request.  JX_EDEVICE if the client has failed (a launch
+ * holding one of its steps failed). */
 jx_status jx_server_submit(jx_server* srv, int32_t client, const uint8_t* actions_host,
                            uint64_t* ticket);
 
 /* Waits for a request (timeout_s < 0: forever; 0: poll, JX_EBUSY if not done)
  * and copies its frames (n_envs * H * W * 3 bytes), rewards and dones into
- * host buffers (each nullable).  latency_s (nullable) = submit-to-complete
- * seconds. */
+ * host buffers (each nullable; all NULL for a client opened with
+ * jx_server_open_dev).  latency_s (nullable) = submit-to-complete seconds.
+ * A failed launch fails its own requests only: they return JX_EDEVICE, their
+ * clients fail (their queued and later requests return JX_EDEVICE too, since
+ * their state is unknown) and every other client is served on. */
 jx_status jx_server_wait(jx_server* srv, uint64_t ticket, double timeout_s, uint8_t* obs_host,
                          float* reward_host, uint8_t* done_host, double* latency_s);
 
@@ -356,7 +378,8 @@ jx_status jx_server_wait_any(jx_server* srv, double timeout_s, uint64_t* ticket,
  * submitted to a closed client. */
 jx_status jx_server_close(jx_server* srv, int32_t client);
 
-/* Counters: launches, requests, envs stepped, admission waits, bytes in use. */
+/* Counters: launches, requests, envs stepped, admission waits, bytes in use,
+ * failed launches. */
 typedef struct {
   int64_t launches;
   int64_t requests;
@@ -365,6 +388,7 @@ typedef struct {
   int64_t bytes_in_use;
   int64_t clients_active;
   int64_t clients_pending;
+  int64_t failed_launches;
 } jx_server_stats;
 jx_status jx_server_get_stats(jx_server* srv, jx_server_stats* out);
 

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -114,6 +115,8 @@ struct Request {
   int n = 0;
   double t_submit = 0, t_done = 0;
   int status = 0;  // 0 queued, 1 launched, 2 done, 3 failed
+  int slot = -1;   // device-result clients: the ring slot its results went to
+  bool dev = false;  // the client's results stay in its device ring
 };
 
 // PENDING: in the admission queue; ADMITTING: memory reserved, being
@@ -138,6 +141,14 @@ struct Client {
   DevState S{};
   int64_t obs_bytes = 0;
   std::deque<std::shared_ptr<Request>> queue;
+  // device-result clients: the caller's rings of `slots` steps; request k of
+  // the client writes slot k mod slots (requests of one client run in order)
+  uint8_t* dev_obs = nullptr;
+  float* dev_rew = nullptr;
+  uint8_t* dev_done = nullptr;
+  int slots = 0;
+  int64_t launched = 0;  // requests of this client issued so far
+  bool failed = false;   // a launch holding this client failed: its state is unknown
 };
 
 struct Launch {
@@ -196,6 +207,10 @@ struct jx_server {
   uint64_t next_ticket = 1;
   int next_client = 0;
   bool stop = false;
+  // testing hook (JX_SERVER_FAIL_LAUNCH): the launch with this index is treated
+  // as failed before any HIP call is made for it; -1 = none
+  int64_t fail_launch = -1;
+  int64_t launches_issued = 0;
   std::string fatal;
   jx_server_stats stats{};
   std::thread sched, comp, admitter;
@@ -235,6 +250,12 @@ LaunchPlan plan_launch(const std::vector<Client*>& batch) {
   }
   P.results = o;
   for (Client* c : batch) {
+    if (c->dev_obs) {  // results go to the client's device ring: no staging
+      P.obs.push_back(-1);
+      P.rew.push_back(-1);
+      P.done.push_back(-1);
+      continue;
+    }
     P.obs.push_back(o);
     o += align256(c->obs_bytes);
     P.rew.push_back(o);
@@ -248,8 +269,9 @@ LaunchPlan plan_launch(const std::vector<Client*>& batch) {
 
 // Upper bound of what one more client adds to a launch's staging.
 int64_t stage_bound(const Client* c) {
-  return align256(sizeof(DevState)) + align256(sizeof(DevIo)) + align256(8 * (int64_t)c->n) +
-         2 * align256(c->n) + align256(c->obs_bytes) + align256(4 * (int64_t)c->n);
+  const int64_t results = c->dev_obs ? 0 : align256(c->obs_bytes) + align256(4 * (int64_t)c->n) + align256(c->n);
+  return align256(sizeof(DevState)) + align256(sizeof(DevIo)) + align256(8 * (int64_t)c->n) + align256(c->n) +
+         results;
 }
 
 // Uploads the client's image (built at open) and runs the episode-0 reset.
@@ -364,6 +386,7 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
   range->len = P.total;
   range->left = (int)batch.size();
   std::vector<DevState> states(batch.size());
+  std::vector<DevIo> dev_io(batch.size());  // I/O of each client, device addresses
   int n_items = 0;
   for (size_t j = 0; j < batch.size(); ++j) {
     Client* c = batch[j];
@@ -374,9 +397,25 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
     r->n = c->n;
     r->obs_bytes = c->obs_bytes;
     r->range = range;
-    r->h_obs = h + P.obs[j];
-    r->h_rew = (float*)(h + P.rew[j]);
-    r->h_done = h + P.done[j];
+    DevIo io{};
+    io.mode = MODE_STEP;
+    io.act = d + P.act[j];
+    if (c->dev_obs) {
+      // the client's k-th request writes ring slot k mod slots
+      r->slot = (int)(c->launched % c->slots);
+      io.obs = c->dev_obs + (int64_t)r->slot * c->obs_bytes;
+      io.rew = c->dev_rew + (int64_t)r->slot * c->n;
+      io.done = c->dev_done + (int64_t)r->slot * c->n;
+    } else {
+      r->h_obs = h + P.obs[j];
+      r->h_rew = (float*)(h + P.rew[j]);
+      r->h_done = h + P.done[j];
+      io.obs = d + P.obs[j];
+      io.rew = reinterpret_cast<float*>(d + P.rew[j]);
+      io.done = d + P.done[j];
+    }
+    c->launched += 1;
+    dev_io[j] = io;
     L.reqs.push_back(r);
     states[j] = c->S;
     n_items += c->n;
@@ -384,6 +423,7 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
   ss.busy = true;
   const bool plain = s->mode == JX_SERVE_PLAIN;
   const int side = batch[0]->cfg.side;
+  const bool inject = s->launches_issued++ == s->fail_launch;
   lk.unlock();
   // descriptors, work items and actions into the pinned range
   DevIo* ios = reinterpret_cast<DevIo*>(h + P.ios);
@@ -392,49 +432,63 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
   for (size_t j = 0; j < batch.size(); ++j) {
     Request* r = L.reqs[j].get();
     std::memcpy(h + P.act[j], r->actions.data(), (size_t)r->n);
-    DevIo io{};
-    io.mode = MODE_STEP;
-    io.act = d + P.act[j];
-    io.obs = d + P.obs[j];
-    io.rew = reinterpret_cast<float*>(d + P.rew[j]);
-    io.done = d + P.done[j];
-    ios[j] = io;
+    ios[j] = dev_io[j];
     if (!plain)
       for (int e = 0; e < r->n; ++e) items[it++] = ServeItem{(int32_t)j, e};
   }
   hipStream_t st = ss.s;
-  bool ok;
-  if (plain) {  // the per-request kernel takes its state and I/O by value: copy the actions only
-    ok = hipMemcpyAsync(d + P.acts, h + P.acts, (size_t)(P.results - P.acts), hipMemcpyHostToDevice, st) ==
-         hipSuccess;
-  } else {
-    std::memcpy(h + P.states, states.data(), sizeof(DevState) * states.size());
-    ok = hipMemcpyAsync(d, h, (size_t)P.results, hipMemcpyHostToDevice, st) == hipSuccess;
+  // an injected failure makes no HIP call for this launch
+  bool ok = false;
+  bool ran = false;  // the serving kernel was enqueued: it used counter set seq
+  if (!inject) {
+    if (plain) {
+      // the per-request kernel takes its state and I/O by value: copy the actions only
+      ok = hipMemcpyAsync(d + P.acts, h + P.acts, (size_t)(P.results - P.acts), hipMemcpyHostToDevice, st) ==
+           hipSuccess;
+      ok = ok && launch_batch(states[0], ios[0], nullptr, 0, LaunchCfg{0, 1, 1, 0}, side, s->n_cu, 0, st) == 0;
+    } else {
+      std::memcpy(h + P.states, states.data(), sizeof(DevState) * states.size());
+      ok = hipMemcpyAsync(d, h, (size_t)P.results, hipMemcpyHostToDevice, st) == hipSuccess;
+      const int wpb = 2;
+      int groups = std::min((n_items + wpb - 1) / wpb, s->n_cu * 4);
+      groups = std::max(groups, 1);
+      ran = ok && launch_serve(reinterpret_cast<DevState*>(d + P.states), reinterpret_cast<DevIo*>(d + P.ios),
+                               reinterpret_cast<ServeItem*>(d + P.items), n_items, ss.d_counters, ss.seq, wpb,
+                               groups, st) == 0;
+      ok = ran;
+    }
+    // results of host-result clients back to the pinned range (none when every
+    // client of the launch keeps its results on the device)
+    if (P.total > P.results)
+      ok = ok && hipMemcpyAsync(h + P.results, d + P.results, (size_t)(P.total - P.results),
+                                hipMemcpyDeviceToHost, st) == hipSuccess;
+    ok = ok && hipEventRecord(ss.ev, st) == hipSuccess;
+    // a launch that failed part-way may still have work queued on the stream:
+    // drain it before the slot and the staging range can be reused
+    if (!ok) hipStreamSynchronize(st);
   }
-  if (plain) {
-    ok = ok && launch_batch(states[0], ios[0], nullptr, 0, LaunchCfg{0, 1, 1, 0}, side, s->n_cu, 0, st) == 0;
-  } else {
-    const int wpb = 2;
-    int groups = std::min((n_items + wpb - 1) / wpb, s->n_cu * 4);
-    groups = std::max(groups, 1);
-    ok = ok && launch_serve(reinterpret_cast<DevState*>(d + P.states), reinterpret_cast<DevIo*>(d + P.ios),
-                            reinterpret_cast<ServeItem*>(d + P.items), n_items, ss.d_counters, ss.seq, wpb,
-                            groups, st) == 0;
-  }
-  ok = ok && hipMemcpyAsync(h + P.results, d + P.results, (size_t)(P.total - P.results), hipMemcpyDeviceToHost,
-                            st) == hipSuccess;
-  ok = ok && hipEventRecord(ss.ev, st) == hipSuccess;
   lk.lock();
-  if (!plain && ok) ss.seq += 1;
+  if (ran) ss.seq += 1;
   if (!ok) {
-    s->fatal = "launch failed";
+    // the launch's requests fail and its clients' state is unknown: those
+    // clients fail (their queued requests too), every other client goes on
     for (auto& r : L.reqs) {
       r->status = 3;
       s->completed.emplace_back(r->ticket, r->client);
     }
-    for (Client* c : batch) c->in_flight = false;
+    for (Client* c : batch) {
+      c->in_flight = false;
+      c->failed = true;
+      for (auto& r : c->queue) {
+        r->status = 3;
+        s->completed.emplace_back(r->ticket, r->client);
+      }
+      c->queue.clear();
+    }
+    s->stats.failed_launches += 1;
     ss.busy = false;
     s->cv_done.notify_all();
+    s->cv_sched.notify_one();
     return;
   }
   s->stats.launches += 1;
@@ -581,6 +635,13 @@ jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_by
   s->mode = mode;
   s->max_batch_envs = max_batch_envs;
   s->budget = (int64_t)hbm_budget_bytes;
+  // testing hook: JX_SERVER_FAIL_LAUNCH=k treats this server's k-th launch
+  // (0-based) as failed without making any HIP call for it
+  if (const char* f = std::getenv("JX_SERVER_FAIL_LAUNCH")) {
+    char* end = nullptr;
+    const long long k = std::strtoll(f, &end, 10);
+    if (end != f && *end == '\0' && k >= 0) s->fail_launch = (int64_t)k;
+  }
   hipDeviceProp_t p;
   SRV_CHK(hipGetDeviceProperties(&p, device), "device properties");
   s->n_cu = std::max(1, p.multiProcessorCount);
@@ -634,8 +695,14 @@ void jx_server_destroy(jx_server* s) {
   delete s;
 }
 
-jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, const jx_env_cfg* cfg,
-                         int32_t* client) {
+}  // extern "C"
+
+namespace {
+
+// Opens a client; dev_obs != nullptr: its results go to the caller's device
+// rings of `slots` steps.
+jx_status open_client(jx_server* s, int32_t n_envs, const uint64_t* seeds, const jx_env_cfg* cfg,
+                      uint8_t* dev_obs, float* dev_rew, uint8_t* dev_done, int32_t slots, int32_t* client) {
   if (!s || !seeds || !cfg || !client) return set_error(JX_EINVAL, "null argument");
   if (n_envs < 1 || n_envs > kMaxItemsPerLaunch) return set_error(JX_EINVAL, "n_envs out of range");
   std::string why;
@@ -649,6 +716,10 @@ jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, co
     c->cfg.ascii_map = c->ascii.c_str();
   }
   c->seeds.assign(seeds, seeds + n_envs);
+  c->dev_obs = dev_obs;
+  c->dev_rew = dev_rew;
+  c->dev_done = dev_done;
+  c->slots = dev_obs ? slots : 0;
   c->bytes = client_bytes(n_envs, *cfg, &c->L, &c->obs_bytes);
   if (c->bytes > s->budget) return set_error(JX_ENOMEM, "client exceeds the HBM budget on its own");
   {
@@ -704,6 +775,25 @@ jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, co
   return JX_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+jx_status jx_server_open(jx_server* s, int32_t n_envs, const uint64_t* seeds, const jx_env_cfg* cfg,
+                         int32_t* client) {
+  return open_client(s, n_envs, seeds, cfg, nullptr, nullptr, nullptr, 0, client);
+}
+
+jx_status jx_server_open_dev(jx_server* s, int32_t n_envs, const uint64_t* seeds, const jx_env_cfg* cfg,
+                             uint8_t* obs_dev, float* reward_dev, uint8_t* done_dev, int32_t slots,
+                             int32_t* client) {
+  if (!obs_dev || !reward_dev || !done_dev) return set_error(JX_EINVAL, "device result rings must not be null");
+  if (slots < 1) return set_error(JX_EINVAL, "slots must be >= 1");
+  if (((uintptr_t)obs_dev & 3) || ((uintptr_t)reward_dev & 3))
+    return set_error(JX_EINVAL, "obs and reward rings must be 4-byte aligned");
+  return open_client(s, n_envs, seeds, cfg, obs_dev, reward_dev, done_dev, slots, client);
+}
+
 jx_status jx_server_submit(jx_server* s, int32_t client, const uint8_t* actions, uint64_t* ticket) {
   if (!s || !actions || !ticket) return set_error(JX_EINVAL, "null argument");
   auto r = std::make_shared<Request>();
@@ -713,7 +803,9 @@ jx_status jx_server_submit(jx_server* s, int32_t client, const uint8_t* actions,
   if (it == s->clients.end() || it->second->closing || it->second->st == CLOSED)
     return set_error(JX_EINVAL, "unknown or closed client");
   Client* c = it->second.get();
+  if (c->failed) return set_error(JX_EDEVICE, "client failed: a launch holding one of its steps failed");
   r->ticket = s->next_ticket++;
+  r->dev = c->dev_obs != nullptr;
   r->client = client;
   r->actions.assign(actions, actions + c->n);
   r->t_submit = now_s();
@@ -734,6 +826,8 @@ jx_status jx_server_wait(jx_server* s, uint64_t ticket, double timeout_s, uint8_
     auto it = s->requests.find(ticket);
     if (it == s->requests.end()) return set_error(JX_EINVAL, "unknown ticket");
     r = it->second;
+    if (r->dev && (obs || rew || done))
+      return set_error(JX_EINVAL, "the client keeps its results in its device rings: pass no host buffers");
     auto finished = [&] { return r->status >= 2; };
     if (timeout_s < 0) {
       s->cv_done.wait(lk, finished);
@@ -757,7 +851,10 @@ jx_status jx_server_wait(jx_server* s, uint64_t ticket, double timeout_s, uint8_
     release_staging(s, r.get());
   }
   s->cv_sched.notify_one();
-  if (failed) return set_error(JX_EDEVICE, fatal.empty() ? "request failed" : fatal);
+  if (failed)
+    return set_error(JX_EDEVICE, fatal.empty() ? "request failed: the launch holding it (or an earlier step of its "
+                                                 "client) failed"
+                                               : fatal);
   return JX_OK;
 }
 
@@ -855,6 +952,7 @@ jx_status jx_server_replay(jx_server* s, int32_t n, const double* t_arrival_s, c
         fail("wait_any failed");
         return;
       }
+      bool dev = false;
       {
         // the buffers are sized for the trace's clients: a request of another
         // caller (which the replay must not run beside) would not fit
@@ -864,9 +962,12 @@ jx_status jx_server_replay(jx_server* s, int32_t n, const double* t_arrival_s, c
           fail("replay: a request not of the trace completed during the replay");
           return;
         }
+        dev = it->second->dev;
       }
       double lat = 0.0;
-      if (jx_server_wait(s, tk, -1.0, obs.data(), rew.data(), dn.data(), &lat) != JX_OK) {
+      // device-result clients: the results stay in their rings, nothing to copy
+      if (jx_server_wait(s, tk, -1.0, dev ? nullptr : obs.data(), dev ? nullptr : rew.data(),
+                         dev ? nullptr : dn.data(), &lat) != JX_OK) {
         fail("a request failed");
         return;
       }

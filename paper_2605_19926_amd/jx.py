@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjx.so")
 
 JX_OK, JX_EINVAL, JX_ENOMEM, JX_EDEVICE, JX_ESTATE, JX_EBUSY = 0, -1, -2, -3, -4, -5
-ABI_VERSION = 4  # the jx_env_cfg layout and signatures this binding marshals
+ABI_VERSION = 5  # the jx_env_cfg layout and signatures this binding marshals
 JX_FORM_PLAIN, JX_FORM_PERSISTENT, JX_FORM_PIPELINE = 0, 1, 2
 JX_ROLLOUT_GRAPH, JX_ROLLOUT_FUSED = 1, 2
 JX_SERVE_COALESCE, JX_SERVE_PLAIN = 0, 1
@@ -69,7 +69,7 @@ class jx_server_stats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("requests", ctypes.c_int64),
                 ("env_steps", ctypes.c_int64), ("admission_waits", ctypes.c_int64),
                 ("bytes_in_use", ctypes.c_int64), ("clients_active", ctypes.c_int64),
-                ("clients_pending", ctypes.c_int64)]
+                ("clients_pending", ctypes.c_int64), ("failed_launches", ctypes.c_int64)]
 
 
 COL_DEBUG_DTYPE = np.dtype([("hit", "<i4"), ("side", "<i4"), ("t", "<f4"), ("cell", "<i4")])
@@ -107,6 +107,8 @@ _SIGS = {
     "jx_server_create": (_i32, [ctypes.POINTER(_vp), _i32, _sz, _i32, _i32, _i32]),
     "jx_server_destroy": (None, [_vp]),
     "jx_server_open": (_i32, [_vp, _i32, _vp, ctypes.POINTER(jx_env_cfg), ctypes.POINTER(_i32)]),
+    "jx_server_open_dev": (_i32, [_vp, _i32, _vp, ctypes.POINTER(jx_env_cfg), _vp, _vp, _vp, _i32,
+                                  ctypes.POINTER(_i32)]),
     "jx_server_submit": (_i32, [_vp, _i32, _vp, ctypes.POINTER(_u64)]),
     "jx_server_wait": (_i32, [_vp, _u64, ctypes.c_double, _vp, _vp, _vp,
                               ctypes.POINTER(ctypes.c_double)]),
@@ -439,6 +441,27 @@ class Server:
         self.sizes[cid.value] = (int(seeds.shape[0]), cfg["obs_h"] * cfg["obs_w"] * 3)
         return cid.value, rc == JX_OK
 
+    def open_dev(self, seeds, cfg: dict, obs, reward, done, slots: int) -> tuple[int, bool]:
+        """A client whose results stay in device rings (torch tensors on the
+        server's device): obs [slots * n * H * W * 3] uint8, reward [slots * n]
+        float32, done [slots * n] uint8; request k writes slot k mod slots.
+        Returns (client id, admitted now)."""
+        seeds = np.ascontiguousarray(seeds, np.uint64)
+        n = int(seeds.shape[0])
+        fb = cfg["obs_h"] * cfg["obs_w"] * 3
+        _need("obs", obs, slots * n * fb)
+        _need("reward", reward, 4 * slots * n)
+        _need("done", done, slots * n)
+        c = make_cfg(cfg)
+        cid = _i32()
+        rc = lib().jx_server_open_dev(self.h, n, seeds.ctypes.data, ctypes.byref(c), _ptr(obs), _ptr(reward),
+                                      _ptr(done), slots, ctypes.byref(cid))
+        if rc not in (JX_OK, JX_EBUSY):
+            check(rc)
+        self.sizes[cid.value] = (n, fb)
+        self.dev_clients = getattr(self, "dev_clients", set()) | {cid.value}
+        return cid.value, rc == JX_OK
+
     def submit(self, client: int, actions: np.ndarray) -> int:
         a = np.ascontiguousarray(actions, np.uint8)
         t = _u64()
@@ -450,6 +473,14 @@ class Server:
         """Returns (obs [n, H*W*3] or None, reward, done, latency_s), or None on
         timeout.  `out` = (obs, reward, done) arrays to fill instead of new ones."""
         n, fb = self.sizes[client]
+        if client in getattr(self, "dev_clients", ()):
+            # results are in the client's device rings: wait only
+            lat = ctypes.c_double()
+            rc = lib().jx_server_wait(self.h, ticket, timeout, None, None, None, ctypes.byref(lat))
+            if rc == JX_EBUSY:
+                return None
+            check(rc)
+            return None, None, None, lat.value
         if out is not None:
             obs, rew, done = out
             if (obs is not None and (obs.dtype != np.uint8 or obs.size != n * fb or

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(jx):
 
 
 def test_abi_version(jx):
-    assert jx.lib().jx_abi_version() == jx.ABI_VERSION == 4
+    assert jx.lib().jx_abi_version() == jx.ABI_VERSION == 5
 
 
 @pytest.mark.parametrize("side", [5, 8, 9, 16, 31, 32, 64])

@@ -481,3 +481,101 @@ def test_serving_admission_by_budget():
     assert st["admission_waits"] >= 2
     assert st["clients_pending"] == 0
     srv.close()
+
+
+def test_serving_device_results_equal_host_results():
+    """A client opened with device result rings gets, in its ring slot k mod
+    slots, exactly the frames, rewards and dones a host-result client of the
+    same envs and actions gets copied to the host; in a coalesced mix with
+    other clients and in the plain per-request mode.  Nothing is copied to the
+    host for it."""
+    import torch
+    from paper_2605_19926_amd import jx
+    cfg = W.env_cfg(side=20, loop_frac=0.1, goal_sprite=1, key_door=1, obs_h=84, obs_w=84, episode_cap=9)
+    n, T, slots = 29, 7, 3
+    seeds = W.seeds(17, n)
+    acts = W.actions(17, T, n, 6)
+    fb = 84 * 84 * 3
+    for mode in (jx.JX_SERVE_COALESCE, jx.JX_SERVE_PLAIN):
+        srv = jx.Server(hbm_budget=1 << 30, n_streams=3, mode=mode)
+        hcid, _ = srv.open(seeds, cfg)
+        ring_o = torch.zeros(slots * n * fb, dtype=torch.uint8, device="cuda")
+        ring_r = torch.zeros(slots * n, dtype=torch.float32, device="cuda")
+        ring_d = torch.zeros(slots * n, dtype=torch.uint8, device="cuda")
+        dcid, _ = srv.open_dev(seeds, cfg, ring_o, ring_r, ring_d, slots)
+        other, _ = srv.open(W.seeds(18, 5), W.env_cfg(side=9, obs_h=64, obs_w=64))
+        for t in range(T):
+            tk_o = srv.submit(other, W.actions(18, 1, 5, 6, stream=t)[0])
+            tk_h = srv.submit(hcid, acts[t])
+            tk_d = srv.submit(dcid, acts[t])
+            host = srv.wait(hcid, tk_h)
+            got = srv.wait(dcid, tk_d)
+            assert got[0] is None and got[3] >= 0.0
+            srv.wait(other, tk_o, want_obs=False)
+            k = t % slots
+            o = ring_o[k * n * fb:(k + 1) * n * fb].cpu().numpy().reshape(n, fb)
+            assert np.array_equal(o, host[0]), f"mode {mode} step {t}: frames differ"
+            assert np.array_equal(ring_r[k * n:(k + 1) * n].cpu().numpy(), host[1])
+            assert np.array_equal(ring_d[k * n:(k + 1) * n].cpu().numpy(), host[2])
+        # host buffers are refused for a device-result client
+        tk = srv.submit(dcid, acts[0])
+        with pytest.raises(jx.JxError) as e:
+            lib = jx.lib()
+            buf = np.zeros(n, np.float32)
+            jx.check(lib.jx_server_wait(srv.h, tk, -1.0, None, buf.ctypes.data, None, None))
+        assert e.value.code == jx.JX_EINVAL
+        assert srv.wait(dcid, tk) is not None   # still collectable without buffers
+        srv.close()
+
+
+def test_serving_injected_launch_failure_fails_only_its_clients(monkeypatch):
+    """JX_SERVER_FAIL_LAUNCH=1 makes the server's second launch fail on the
+    host (no HIP call is made for it).  Only that launch's request and client
+    fail; the other clients are served on and their results equal an
+    unfailed server's."""
+    from paper_2605_19926_amd import jx
+    cfg = W.env_cfg(side=12, goal_sprite=1, obs_h=32, obs_w=32, episode_cap=50)
+    sa, sb, sc = W.seeds(81, 6), W.seeds(82, 4), W.seeds(83, 9)
+    T = 4
+    acts = {k: W.actions(80 + k, T, n, 6) for k, n in ((0, 6), (1, 4), (2, 9))}
+
+    def run(fail: bool, mode):
+        if fail:
+            monkeypatch.setenv("JX_SERVER_FAIL_LAUNCH", "1")
+        else:
+            monkeypatch.delenv("JX_SERVER_FAIL_LAUNCH", raising=False)
+        srv = jx.Server(hbm_budget=1 << 28, n_streams=2, mode=mode)
+        monkeypatch.delenv("JX_SERVER_FAIL_LAUNCH", raising=False)
+        a, _ = srv.open(sa, cfg)
+        b, _ = srv.open(sb, cfg)
+        c, _ = srv.open(sc, cfg)
+        out = {a: [], c: []}
+        # one request in flight at a time: launch i holds request i alone
+        for t in range(T):
+            for cid, k in ((a, 0), (b, 1), (c, 2)):
+                if fail and cid == b and t > 0:
+                    with pytest.raises(jx.JxError) as e:   # the failed client takes no more steps
+                        srv.submit(cid, acts[k][t])
+                    assert e.value.code == jx.JX_EDEVICE
+                    continue
+                tk = srv.submit(cid, acts[k][t])
+                if fail and cid == b and t == 0:
+                    with pytest.raises(jx.JxError) as e:
+                        srv.wait(cid, tk)
+                    assert e.value.code == jx.JX_EDEVICE
+                    continue
+                res = srv.wait(cid, tk)
+                if cid in out:
+                    out[cid].append(res[:3])
+        st = srv.stats()
+        srv.close()
+        return out, st
+
+    for mode in (jx.JX_SERVE_PLAIN, jx.JX_SERVE_COALESCE):
+        ref, st_ref = run(False, mode)
+        got, st = run(True, mode)
+        assert st_ref["failed_launches"] == 0 and st["failed_launches"] == 1
+        for cid in ref:
+            for t in range(T):
+                for k in range(3):
+                    assert np.array_equal(got[cid][t][k], ref[cid][t][k]), (mode, cid, t, k)
