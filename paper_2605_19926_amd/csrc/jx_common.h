@@ -1,5 +1,7 @@
 // jx_common.h -- helpers shared by the host translation units.
 #pragma once
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <string>
 #include <vector>
 
@@ -7,6 +9,17 @@
 #include "jx_internal.h"
 
 namespace jx {
+// A named roctx range for the lifetime of the object: rocprofv3
+// --marker-trace shows the library's calls (reset, step, rollout, render,
+// serving launches) beside the kernels they enqueue; without a tracer the
+// calls are no-ops.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
 jx_status set_error(jx_status code, const std::string& msg);
 bool validate_cfg(const jx_env_cfg& c, std::string* why);
 // Frame format of a configuration (obs_layout * 3 + obs_dtype) and its frame bytes.
@@ -23,4 +36,10 @@ void set_uniform(DevState* s, const jx_env_cfg* cfgs, int n_cfgs, const std::vec
 jx_status build_image(int n, const uint64_t* seeds, const jx_env_cfg* cfgs, int n_cfgs,
                       const int32_t* cfg_index, std::vector<uint8_t>* img, Layout* L,
                       std::vector<int64_t>* obs_off, std::vector<int32_t>* idx);
+// JX_OK when the state image b (laid out as L) may be loaded into a context of
+// n envs with these configurations, else JX_EINVAL with the reason.
+jx_status check_state_image(const uint8_t* b, const Layout& L, int n, const std::vector<jx_env_cfg>& cfgs,
+                            const std::vector<int32_t>& cfg_idx);
+// Thread-local message of the last error (jx_last_error).
+extern thread_local std::string g_last_error;
 }  // namespace jx

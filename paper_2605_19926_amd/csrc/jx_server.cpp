@@ -425,6 +425,7 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
   const int side = batch[0]->cfg.side;
   const bool inject = s->launches_issued++ == s->fail_launch;
   lk.unlock();
+  TraceRange trace(plain ? "jx_server launch (plain)" : "jx_server launch (coalesced)");
   // descriptors, work items and actions into the pinned range
   DevIo* ios = reinterpret_cast<DevIo*>(h + P.ios);
   ServeItem* items = reinterpret_cast<ServeItem*>(h + P.items);
