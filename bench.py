@@ -93,6 +93,25 @@ def measured_traffic(form: str, digest: str):
         return None
 
 
+def store_pattern_ceilings():
+    """GB/s that constant-data store patterns reach on this device (the
+    library's jx_store_ceiling program, run in its own process): the fastest
+    linear fill pattern, and the renderer's own pattern of one 64x64 frame per
+    wave and step.  None if the program is missing or fails."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2605_19926_amd", "jx_store_ceiling")
+    if not os.path.exists(exe):
+        return None
+    try:
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    except subprocess.TimeoutExpired:
+        return None
+    if r.returncode != 0:
+        progress(f"store ceiling calibration failed: {r.stderr.strip()[-200:]}")
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def _oracle_chunk(args):
     cfg_d, seeds, acts = args
     import oracle
@@ -282,6 +301,46 @@ def serve_form(jx, n_requests: int, mode: int, rate: float = W.SERVE["rate"],
             "wall_s": wall}
 
 
+def shape_sweep(jx, torch) -> list[dict]:
+    """Fused 128-step rollouts of one configuration (16x16 mazes) over frame
+    size x env count, under the static-stride and persistent mappings: how many
+    envs one wave per env needs before the frame writes saturate, i.e. where
+    splitting an env over several waves or packing several envs into one wave
+    could pay off."""
+    T = 128
+    out = []
+    for side_px in (32, 64, 128):
+        for n in (256, 512, 1024, 2048, 4096, 8192, 16384):
+            cfg = W.env_cfg(side=16, loop_frac=0.1, goal_sprite=1, obs_h=side_px, obs_w=side_px,
+                            n_actions=6, episode_cap=512)
+            env = jx.Env(W.seeds(3, n), cfg)
+            env.reset()
+            ob = env.obs_bytes
+            o = torch.empty(T * ob, dtype=torch.uint8, device=env.dev)
+            rew = torch.empty(T * n, dtype=torch.float32, device=env.dev)
+            dn = torch.empty(T * n, dtype=torch.uint8, device=env.dev)
+            acts = torch.from_numpy(W.actions(3, T, n, 6)).to(env.dev)
+            for launch in (dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0),
+                           dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0),
+                           dict(form=1, waves_per_group=4, groups_per_cu=2, store_mode=0)):
+                env.set_launch(**launch)
+                env.rollout(acts, o, rew, dn, T, obs_stride=ob, graph=False, fused=True)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(3):
+                    env.rollout(acts, o, rew, dn, T, obs_stride=ob, graph=False, fused=True)
+                e1.record()
+                torch.cuda.synchronize()
+                sec = e0.elapsed_time(e1) / 1e3
+                out.append({"frame": f"{side_px}x{side_px}", "n_envs": n, "launch": launch,
+                            "env_steps_per_s": n * T * 3 / sec, "obs_gbs": ob * T * 3 / sec / 1e9})
+            env.close()
+            del o
+        progress(f"shape sweep {side_px}x{side_px} done")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,6 +356,8 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the batching and serving forms")
     ap.add_argument("--serve-requests", type=int, default=20_000)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--shape-sweep", action="store_true",
+                    help="only time fused rollouts over frame size x env count and print them")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 launches), to scale "
                          "HBM traffic counters, and exit")
@@ -318,6 +379,10 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb, "launches": 5}))
+        return 0
+
+    if args.shape_sweep:
+        print(json.dumps({"shape_sweep": shape_sweep(jx, torch)}))
         return 0
 
     wl = W.SCALE
@@ -401,6 +466,9 @@ def main() -> int:
     achieved = per_launch / kern_s / 1e9
     tr = measured_traffic(args.form, _kernel_source_digest())
     traffic = None if tr is None else tr * n * K / launches
+    # store-pattern ceilings on this machine: constant-data store patterns timed by
+    # the library's calibration program (its own process and buffer)
+    pattern_ceilings = store_pattern_ceilings()
     # write-only ceiling on this machine: a plain fill of the whole frame ring
     fills = 3
     f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -571,7 +639,10 @@ def main() -> int:
                      "kernel_avg_us": kern_s * 1e6,
                      "kernel_source_sha256_16": _kernel_source_digest(),
                      "write_only_ceiling_gbs": write_ceiling,
-                     "frac_of_write_ceiling": achieved / write_ceiling},
+                     "frac_of_write_ceiling": achieved / write_ceiling,
+                     "store_pattern_ceilings_gbs": pattern_ceilings,
+                     "frac_of_frame_pattern_ceiling": (achieved / pattern_ceilings["env_frames_12B"]
+                                                       if pattern_ceilings else None)},
         "single_slot": single,
         "distance_shading": shaded,
         "ascii_maps": ascii_maps,

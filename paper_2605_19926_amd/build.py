@@ -18,6 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libjx.so")
 DEMO = os.path.join(PKG, "jx_demo")  # a C++ caller of the C-ABI (no Python)
+STORE_CEILING = os.path.join(PKG, "jx_store_ceiling")  # HBM store-pattern calibration
 ARCH = os.environ.get("JX_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -63,6 +64,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"demo build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, DEMO)
+    # store-pattern calibration program (bench.py reports its figures)
+    tmp = STORE_CEILING + ".tmp"
+    cmd = [HIPCC, "-O3", "-std=c++17", "-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
+           "-Xclang", "-packed-fp32-ops", os.path.join(CSRC, "jx_store_ceiling.cpp"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"store ceiling build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, STORE_CEILING)
     if verbose:
         print("built", OUT, "and", DEMO)
     return OUT
