@@ -392,3 +392,75 @@ def test_trajectory_tiny_full(wl):
     assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
     assert exact_frames >= 16 * 3                       # several resets per env were checked
     env.close()
+
+
+def test_batching_form_full_size_persistent_fused():
+    """The batching workload at full size in the launch configuration bench.py
+    times for it: 16,384 envs of mixed shapes (map side 8-64, frames 32^2-128^2,
+    key-door on half) in one persistent fused launch (4 waves x 2 workgroups per
+    compute unit, envs claimed one at a time), with episode clocks set so that
+    every env reaches its cap inside the rollout (a device reset in every env).
+    (a) Every output equals single-step launches from the same start bit for bit
+    (each step's frames compared on the device, rewards, dones, final state);
+    (b) along those single steps 32 sampled envs are checked against the oracle
+    at every step from the shared state."""
+    import torch
+    n, T = W.BATCH["n_envs"], 40
+    cfgs, idx = W.batch_cfgs(n)
+    seeds = W.seeds(W.BATCH["number"], n)
+    acts = W.actions(W.BATCH["number"], T, n, 6)
+    env = U.env_of(cfgs, seeds, idx, obs=False)
+    caps = np.array([c["episode_cap"] for c in cfgs], np.int64)[idx]
+    env.set_state({"t": (caps - 1 - (np.arange(n) % T)).astype(np.uint32)})
+    env.set_launch(form=1, waves_per_group=4, groups_per_cu=2, store_mode=0)
+    snap = env.get_state_bytes()
+    ob = env.obs_bytes
+    act_d = torch.from_numpy(acts).to(env.dev)
+    ring = torch.empty(T * ob, dtype=torch.uint8, device=env.dev)
+    rew = torch.empty(T * n, dtype=torch.float32, device=env.dev)
+    done = torch.empty(T * n, dtype=torch.uint8, device=env.dev)
+    env.rollout(act_d, ring, rew, done, T, obs_stride=ob, graph=False, fused=True)
+    torch.cuda.synchronize()
+    fused_state = env.get_state_bytes()
+    f_rew, f_done = rew.cpu().numpy(), done.cpu().numpy()
+    assert f_done.reshape(T, n).any(axis=0).all(), "every env resets inside the rollout"
+    env.set_state_bytes(snap)
+    env.set_launch(form=0, waves_per_group=1, groups_per_cu=1, store_mode=0)
+    one = torch.empty(ob, dtype=torch.uint8, device=env.dev)
+    r1 = torch.empty(n, dtype=torch.float32, device=env.dev)
+    d1 = torch.empty(n, dtype=torch.uint8, device=env.dev)
+    rng = np.random.default_rng(9)
+    pick = [int(i) for i in np.sort(rng.choice(n, 32, replace=False))]
+    grids = {i: U.oracle_maze(cfgs[idx[i]], seeds[i]) for i in pick}
+    ocs = {i: orc.make_cfg(cfgs[idx[i]]) for i in pick}
+    S_prev = env.get_state()
+    stats = U.FrameStats()
+    skipped = checked = 0
+    errors = []
+    for t in range(T):
+        env.step(act_d[t], one, r1, d1)
+        torch.cuda.synchronize()
+        assert torch.equal(one, ring[t * ob:(t + 1) * ob]), f"step {t}: fused frames differ"
+        r_np, d_np = r1.cpu().numpy(), d1.cpu().numpy()
+        assert np.array_equal(r_np, f_rew[t * n:(t + 1) * n]), f"step {t}: rewards differ"
+        assert np.array_equal(d_np, f_done[t * n:(t + 1) * n]), f"step {t}: dones differ"
+        S = env.get_state()
+        one_np = one.cpu().numpy()
+        for i in pick:
+            c = cfgs[idx[i]]
+            checked += 1
+            g_after = U.gpu_state_dict(S, i)
+            skip, errs, _ = U.compare_step(U.gpu_state_dict(S_prev, i), c, seeds[i], grids[i], acts[t, i],
+                                           g_after, r_np[i], d_np[i], S["events"][i])
+            skipped += int(skip)
+            errors += [f"step {t} env {i}: {e}" for e in errs]
+            U.check_frame(stats, U.frame_of(one_np, env.obs_offsets, i, c["obs_h"], c["obs_w"]), grids[i],
+                          ocs[i], orc.state_from(g_after), tag=f"step {t} env {i}")
+        S_prev = S
+    assert np.array_equal(env.get_state_bytes(), fused_state), "final state differs"
+    assert not errors, errors[:10]
+    assert skipped <= max(2, checked // 50), f"too many flagged steps: {skipped}"
+    stats.report(f"persistent-fused/{W.BATCH['name']}")
+    assert not stats.mismatch, stats.mismatch[:10]
+    assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
+    env.close()
