@@ -201,7 +201,9 @@ jx_status jx_obs_offsets(const jx_ctx* ctx, int64_t* offsets_host);
  * uint8.  prev_action_dev (nullable) [n] uint8 receives the previous action to
  * feed the policy beside the returned frame (the paper's agent concatenates
  * it): the action taken, or n_actions ("none") when the frame starts a new
- * episode (done = 1) or the action was out of range. */
+ * episode (done = 1) or the action was out of range.  A caller may capture the
+ * call into a graph of its own under any launch mapping: every launch leaves
+ * the work-queue counters it used at zero, so replays find them clean. */
 jx_status jx_step(jx_ctx* ctx, const uint8_t* actions_dev, uint8_t* obs_dev, float* reward_dev,
                   uint8_t* done_dev, uint8_t* prev_action_dev);
 

@@ -1165,7 +1165,8 @@ __global__ __launch_bounds__(64 * WPB) void k_plain(DevState S, DevIo io0, const
   process_env<MAXN, ASC, FMT>(S, io, env, lane, smap[w], sclr, scvt, scol[w]);
 }
 
-// Work distribution of the persistent forms.  Items (positions in a work
+// Work distribution of the persistent forms (word 0 of a queue's line counts
+// claims, word 1 the waves that left it).  Items (positions in a work
 // order) are split over up to 32 queues by position modulo the queue count; a
 // workgroup serves queue blockIdx % nq (so each queue is served from one XCD),
 // and the queues (one 128-byte line each) sit in different L2 channels: their
@@ -1196,7 +1197,8 @@ __device__ __forceinline__ QueueView queue_view(uint32_t* queues, uint32_t seq, 
   v.chunk = c < 1 ? 1 : (c > max_chunk ? max_chunk : c);
   if (blockIdx.x == 0 && w == 0 && lane < kQueues) {
     const int nxt = (int)((seq + 1) % kQueueSlots);
-    queues[(nxt * kQueues + lane) * kQueueStride] = 0u;
+    queues[(nxt * kQueues + lane) * kQueueStride] = 0u;       // claims
+    queues[(nxt * kQueues + lane) * kQueueStride + 1] = 0u;   // exits
   }
   return v;
 }
@@ -1218,6 +1220,17 @@ __device__ __forceinline__ void queue_drain(const QueueView& v, int lane, F&& f)
     uint32_t got = 0;
     if (lane == 0) got = atomicAdd(v.ctr, (uint32_t)v.chunk);
     first = dyn0 + __builtin_amdgcn_readfirstlane((int)got);
+  }
+  // The last wave to leave the queue returns its claim and exit counters to
+  // zero, so every launch leaves its counter set clean and a launch captured
+  // once replays correctly.  A wave counts its exit only after its last claim
+  // has returned, so no claim can follow the reset.
+  if (lane == 0) {
+    const uint32_t left = atomicAdd(v.ctr + 1, 1u);
+    if (left == (uint32_t)v.waves - 1u) {
+      __hip_atomic_store(v.ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(v.ctr + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 

@@ -579,3 +579,56 @@ def test_serving_injected_launch_failure_fails_only_its_clients(monkeypatch):
             for t in range(T):
                 for k in range(3):
                     assert np.array_equal(got[cid][t][k], ref[cid][t][k]), (mode, cid, t, k)
+
+
+def test_persistent_step_captured_by_the_caller_replays_correctly():
+    """A caller captures one jx_step under the persistent mapping (work queues)
+    into its own graph and replays it several times, with eager launches and
+    synchronisations between the replays.  Each replay must equal an eager plain
+    step from the same state: the queue counters a launch used are back at zero
+    when it ends, so a replay finds them clean."""
+    import torch
+    from paper_2605_19926_amd import jx
+    n = 1536
+    cfgs, idx = W.batch_cfgs(n, number=41)
+    s = torch.cuda.Stream()
+    env = jx.Env(W.seeds(41, n), cfgs, idx, stream=s)
+    with torch.cuda.stream(s):
+        env.reset()
+        ob = env.obs_bytes
+        acts = torch.zeros(n, dtype=torch.uint8, device=env.dev)
+        obs = torch.zeros(ob, dtype=torch.uint8, device=env.dev)
+        rew = torch.zeros(n, dtype=torch.float32, device=env.dev)
+        done = torch.zeros(n, dtype=torch.uint8, device=env.dev)
+    s.synchronize()
+    persist = dict(form=1, waves_per_group=2, groups_per_cu=1, store_mode=0)
+    env.set_launch(**persist)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        env.step(acts, obs, rew, done)
+    s.synchronize()
+    ref_obs = torch.zeros_like(obs)
+    ref_rew = torch.zeros_like(rew)
+    ref_done = torch.zeros_like(done)
+    for r in range(4):
+        a = torch.from_numpy(W.actions(41, 1, n, 6, stream=r)[0]).to(env.dev)
+        with torch.cuda.stream(s):
+            acts.copy_(a)
+        s.synchronize()
+        before = env.get_state_bytes()
+        g.replay()
+        s.synchronize()
+        got = (obs.clone(), rew.clone(), done.clone(), env.get_state_bytes())
+        # the same step eagerly, plain mapping, from the same state
+        env.set_state_bytes(before)
+        env.set_launch(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0)
+        with torch.cuda.stream(s):
+            env.step(a, ref_obs, ref_rew, ref_done)
+        s.synchronize()
+        env.set_launch(**persist)
+        assert torch.equal(got[0], ref_obs), f"replay {r}: frames differ"
+        assert torch.equal(got[1], ref_rew) and torch.equal(got[2], ref_done), f"replay {r}: rewards/dones"
+        assert np.array_equal(got[3], env.get_state_bytes()), f"replay {r}: state differs"
+        # leave the env in the replayed state for the next round
+        env.set_state_bytes(got[3])
+    env.close()
