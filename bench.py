@@ -302,10 +302,10 @@ def serve_form(jx, n_requests: int, mode: int, rate: float = W.SERVE["rate"],
 
 def shape_sweep(jx, torch) -> list[dict]:
     """Fused 128-step rollouts of one configuration (16x16 mazes) over frame
-    size x env count, under the static-stride and persistent mappings: how many
-    envs one wave per env needs before the frame writes saturate, i.e. where
-    splitting an env over several waves or packing several envs into one wave
-    could pay off."""
+    size x env count, under the static-stride and persistent mappings with one
+    wave per env and the static stride with 2 or 4 waves per env: how many envs
+    one wave per env needs before the frame writes saturate, and what several
+    waves per env give below that."""
     T = 128
     out = []
     for side_px in (32, 64, 128):
@@ -321,7 +321,9 @@ def shape_sweep(jx, torch) -> list[dict]:
             acts = torch.from_numpy(W.actions(3, T, n, 6)).to(env.dev)
             for launch in (dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0),
                            dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0),
-                           dict(form=1, waves_per_group=4, groups_per_cu=2, store_mode=0)):
+                           dict(form=1, waves_per_group=4, groups_per_cu=2, store_mode=0),
+                           dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0, waves_per_env=2),
+                           dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0, waves_per_env=4)):
                 env.set_launch(**launch)
                 env.rollout(acts, o, rew, dn, T, obs_stride=ob, graph=False, fused=True)
                 torch.cuda.synchronize()

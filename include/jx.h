@@ -125,6 +125,11 @@ typedef struct {
                               (pipelined: 1, 2, 4) per workgroup */
   int32_t groups_per_cu;   /* persistent and pipelined forms: workgroups per compute unit, 1..16 */
   int32_t store_mode;      /* 0: ordinary stores, 1: non-temporal observation stores */
+  int32_t waves_per_env;   /* plain form: 1, 2 or 4 waves share one env (at most
+                              waves_per_group; other forms: 1).  Each runs the same
+                              step and cast and writes its share of the frame's
+                              rows, so small batches of large frames use more of
+                              the chip; results do not change. */
 } jx_launch;
 
 /* Per-column record of the last render (tests and tools).  hit = tile id of the

@@ -46,7 +46,7 @@ struct jx_ctx {
   uint32_t* scratch = nullptr;
   int scratch_err = 0;
   // captured rollouts, keyed by (T, launch mapping)
-  std::map<std::array<int32_t, 5>, hipGraphExec_t> graphs;
+  std::map<std::array<int32_t, 6>, hipGraphExec_t> graphs;
 };
 
 #define HIPCHK(expr)                                                                   \
@@ -306,7 +306,7 @@ jx_status jx_rollout(jx_ctx* c, int32_t T, const uint8_t* actions, uint8_t* obs,
   RolloutDesc d{actions, obs, reward, done, prev_action, obs_stride, c->n, c->launch.store_mode};
   int rc = launch_set_desc(c->S.rdesc, d, c->stream);
   if (rc) return set_error(JX_EDEVICE, std::string("descriptor update: ") + kernel_error_string(rc));
-  const std::array<int32_t, 5> key = {T, c->launch.form, c->launch.waves_per_group,
+  const std::array<int32_t, 6> key = {T, c->launch.form, c->launch.waves_per_group, c->launch.waves_per_env,
                                       c->launch.groups_per_cu, c->launch.store_mode};
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
@@ -489,7 +489,11 @@ jx_status jx_set_launch(jx_ctx* c, const jx_launch* l) {
   if (l->form != JX_FORM_PLAIN && (l->groups_per_cu < 1 || l->groups_per_cu > 16))
     return set_error(JX_EINVAL, "groups_per_cu must be in 1..16");
   if (l->store_mode != 0 && l->store_mode != 1) return set_error(JX_EINVAL, "store_mode must be 0 or 1");
-  c->launch = LaunchCfg{l->form, w, std::max(1, l->groups_per_cu), l->store_mode};
+  const int wpe = l->waves_per_env;
+  if (wpe != 1 && wpe != 2 && wpe != 4) return set_error(JX_EINVAL, "waves_per_env must be 1, 2 or 4");
+  if (wpe > 1 && l->form != JX_FORM_PLAIN) return set_error(JX_EINVAL, "waves_per_env > 1 needs the plain form");
+  if (wpe > w) return set_error(JX_EINVAL, "waves_per_env must not exceed waves_per_group");
+  c->launch = LaunchCfg{l->form, w, std::max(1, l->groups_per_cu), l->store_mode, wpe};
   return JX_OK;
 }
 
@@ -499,6 +503,7 @@ jx_status jx_get_launch(const jx_ctx* c, jx_launch* l) {
   l->waves_per_group = c->launch.waves_per_group;
   l->groups_per_cu = c->launch.groups_per_cu;
   l->store_mode = c->launch.store_mode;
+  l->waves_per_env = c->launch.waves_per_env;
   return JX_OK;
 }
 
@@ -554,7 +559,7 @@ bool cache_lookup(const char* path, const std::string& key, LaunchCfg* out) {
   std::string k;
   LaunchCfg l{};
   bool found = false;
-  while (f >> k >> l.form >> l.waves_per_group >> l.groups_per_cu >> l.store_mode)
+  while (f >> k >> l.form >> l.waves_per_group >> l.groups_per_cu >> l.store_mode >> l.waves_per_env)
     if (k == key) {
       *out = l;
       found = true;
@@ -603,6 +608,9 @@ extern "C" jx_status jx_autotune(jx_ctx* c, const uint8_t* actions, int32_t iter
   std::vector<LaunchCfg> cands;
   for (int w : {1, 2, 4, 8})
     for (int s : {0, 1}) cands.push_back(LaunchCfg{0, w, 1, s});
+  // several waves per env (small batches of large frames)
+  for (int w : {4, 8})
+    for (int e : {2, 4}) cands.push_back(LaunchCfg{0, w, 1, 0, e});
   for (int w : {1, 2, 4})
     for (int g : {2, 4, 8})
       for (int s : {0, 1}) cands.push_back(LaunchCfg{1, w, g, s});
@@ -679,7 +687,7 @@ extern "C" jx_status jx_autotune(jx_ctx* c, const uint8_t* actions, int32_t iter
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << key << " " << best.form << " " << best.waves_per_group << " " << best.groups_per_cu << " "
-      << best.store_mode << "\n";
+      << best.store_mode << " " << best.waves_per_env << "\n";
   }
   if (chosen) jx_get_launch(c, chosen);
   return JX_OK;

@@ -137,6 +137,7 @@ struct Layout {
 // Launch entry points implemented in jx_kernels.hip.
 struct LaunchCfg {
   int32_t form, waves_per_group, groups_per_cu, store_mode;
+  int32_t waves_per_env = 1;  // plain form: waves sharing one env (1, 2, 4; at most waves_per_group)
 };
 // Persistent queues: kQueueSlots counter sets of kQueues queues each, one
 // 128-byte line per counter.  Launch `seq` uses set seq % kQueueSlots and clears

@@ -763,21 +763,22 @@ constexpr int kWaitTwoPairs = 0x0F74;
 // (Q = W / 4 groups, di = 64 / Q), so each lane's group is fixed.
 template <int FMT>
 __device__ void fill_frame_f(const uint32_t* lcol, const uint32_t* lcvt, uint8_t* base, int W, int H, int lane,
-                             int nt) {
+                             int nt, int part, int parts) {
   using F = ObsFmt<FMT>;
   const int Q = W >> 2, H2 = H >> 1;
   const int64_t rowb = F::row_bytes(W), plane = (int64_t)H * W * F::kElem;
   const int di = 64 / Q;
-  int i = lane / Q;
-  const int cq = lane - i * Q;
+  const int cq = lane % Q;
+  int i = lane / Q + part * di;
   if (lane < di * Q) {
     const ColGroupF<FMT> g = col_group_f<FMT>(lcol, lcvt, cq);
     uint8_t* up = base + (int64_t)(H2 - 1 - i) * rowb + F::kGroupBytes * cq;
     uint8_t* dn = base + (int64_t)(H2 + i) * rowb + F::kGroupBytes * cq;
-    const int64_t step = (int64_t)di * rowb;
+    const int pdi = parts * di;
+    const int64_t step = (int64_t)pdi * rowb;
     uint32_t ii = (uint32_t)i * kRowStep;
-    const uint32_t dii = (uint32_t)di * kRowStep;
-    for (; i < H2; i += di) {
+    const uint32_t dii = (uint32_t)pdi * kRowStep;
+    for (; i < H2; i += pdi) {
       emit_pair_f<FMT>(g, (uint32_t)i, ii, up, dn, plane, nt);
       ii += dii;
       up -= step;
@@ -788,28 +789,30 @@ __device__ void fill_frame_f(const uint32_t* lcol, const uint32_t* lcvt, uint8_t
 
 template <int FMT>
 __device__ void fill_frame(const uint32_t* lcol, const uint32_t* lcvt, uint8_t* base, int W, int H, int lane,
-                           int nt) {
+                           int nt, int part = 0, int parts = 1) {
   if constexpr (FMT != 0) {
-    fill_frame_f<FMT>(lcol, lcvt, base, W, H, lane, nt);
+    fill_frame_f<FMT>(lcol, lcvt, base, W, H, lane, nt, part, parts);
     return;
   }
   // lane -> (column group cq, first distance i); the wave's di * Q lanes
   // (all 64 when Q divides 64, 63 of them at W = 84) cover di row pairs of
   // every column group per iteration, so each lane's column group is fixed and
-  // its records stay in registers.
+  // its records stay in registers.  When `parts` waves share the env, wave
+  // `part` takes every parts-th block of di row pairs.
   const int Q = W >> 2, H2 = H >> 1;
   const int rowb = 3 * W;
   const int di = 64 / Q;
-  int i = lane / Q;
-  const int cq = lane - i * Q;
+  const int cq = lane % Q;
+  int i = lane / Q + part * di;
   if (lane < di * Q) {
     const ColGroup g = col_group(lcol, cq);
     uint8_t* up = base + (int64_t)(H2 - 1 - i) * rowb + 12 * cq;
     uint8_t* dn = base + (int64_t)(H2 + i) * rowb + 12 * cq;
-    const int64_t step = (int64_t)di * rowb;
+    const int pdi = parts * di;
+    const int64_t step = (int64_t)pdi * rowb;
     uint32_t ii = (uint32_t)i * kRowStep;
-    const uint32_t dii = (uint32_t)di * kRowStep;
-    for (; i < H2; i += di) {
+    const uint32_t dii = (uint32_t)pdi * kRowStep;
+    for (; i < H2; i += pdi) {
       emit_pair(g, (uint32_t)i, ii, up, dn, nt);
       __builtin_amdgcn_s_waitcnt(kWaitTwoPairs);
       ii += dii;
@@ -1124,16 +1127,20 @@ __device__ __forceinline__ int64_t obs_off_of(const DevState& S, int env) {
 }
 
 // The whole per-env pipeline in one wave.
+// part / parts: this wave is one of `parts` waves sharing the env; each runs
+// the same step and cast, fills its share of the frame's row pairs, and only
+// part 0 writes the state and the step's outputs.
 template <int MAXN, bool ASC, int FMT>
 __device__ __forceinline__ void process_env(const DevState& S, const DevIo& io, int env, int lane, uint8_t* lmap,
-                            const uint32_t* lclr, const uint32_t* lcvt, uint32_t* lcol) {
+                            const uint32_t* lclr, const uint32_t* lcvt, uint32_t* lcol, int part = 0,
+                            int parts = 1) {
   EnvIn<MAXN> in;
   load_env<MAXN>(S, env, lane, in);
   EnvOut o;
   produce_env<MAXN, true, ASC>(in, S, io, -1, lane, lmap, lclr, lcol, o);
   o.obs_off = obs_off_of(S, env);
-  if (io.obs) fill_frame<FMT>(lcol, lcvt, io.obs + o.obs_off, o.W, o.H, lane, io.store_mode);
-  write_back(S, io, o, lane);
+  if (io.obs) fill_frame<FMT>(lcol, lcvt, io.obs + o.obs_off, o.W, o.H, lane, io.store_mode, part, parts);
+  if (part == 0) write_back(S, io, o, lane);
 }
 
 // I/O of this launch: given by value, or (graph replays) from the descriptor.
@@ -1150,19 +1157,21 @@ __device__ __forceinline__ DevIo io_of(const DevIo& io, const RolloutDesc* rd, i
   return r;
 }
 
+// wpe waves per env (1, 2 or 4): consecutive waves share an env.
 template <int MAXN, int WPB, bool ASC, int FMT>
 __global__ __launch_bounds__(64 * WPB) void k_plain(DevState S, DevIo io0, const RolloutDesc* rd,
-                                                    int t) {
+                                                    int t, int wpe) {
   __shared__ __align__(16) uint8_t smap[WPB][MAXN * MAXN];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
   __shared__ uint32_t sclr[kColorWords];
   __shared__ uint32_t scvt[FMT % 3 ? 256 : 1];
   stage_tables<FMT>(sclr, scvt);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  const int env = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + w);
+  const int gw = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + w);
+  const int env = gw / wpe, part = gw - env * wpe;
   if (env >= S.n) return;
   const DevIo io = io_of(io0, rd, t);
-  process_env<MAXN, ASC, FMT>(S, io, env, lane, smap[w], sclr, scvt, scol[w]);
+  process_env<MAXN, ASC, FMT>(S, io, env, lane, smap[w], sclr, scvt, scol[w], part, wpe);
 }
 
 // Work distribution of the persistent forms (word 0 of a queue's line counts
@@ -1333,7 +1342,7 @@ template <int MAXN, bool ASC, int FMT>
 __device__ __forceinline__ void roll_env(const DevState& S, int env, int lane, uint8_t* lmap, const uint32_t* lclr,
                                          const uint32_t* lcvt, uint32_t* lcol, const uint8_t* act, uint8_t* obs,
                                          int64_t obs_stride, float* rew, uint8_t* dn, uint8_t* prv, int T,
-                                         int store_mode, const DevIo& io) {
+                                         int store_mode, const DevIo& io, int part = 0, int parts = 1) {
   const int64_t n = S.n;
   EnvIn<MAXN> in;
   load_env<MAXN>(S, env, lane, in);
@@ -1364,8 +1373,8 @@ __device__ __forceinline__ void roll_env(const DevState& S, int env, int lane, u
       EnvOut o;
       produce_env<MAXN, false, ASC>(in, S, io, a, ln, lmap, lclr, lcol, o);
       const int t = t0 + k;
-      fill_frame<FMT>(lcol, lcvt, obs + (int64_t)t * obs_stride + obs_off, o.W, o.H, ln, store_mode);
-      if (lane == 0) {
+      fill_frame<FMT>(lcol, lcvt, obs + (int64_t)t * obs_stride + obs_off, o.W, o.H, ln, store_mode, part, parts);
+      if (lane == 0 && part == 0) {
         rew[(int64_t)t * n + env] = o.reward;
         dn[(int64_t)t * n + env] = (uint8_t)o.done;
         if (prv) prv[(int64_t)t * n + env] = (uint8_t)o.prev;
@@ -1391,7 +1400,7 @@ __device__ __forceinline__ void roll_env(const DevState& S, int env, int lane, u
       in.cs = uniform_d(o.cs);
     }
   }
-  if (lane == 0 && T > 0) {
+  if (lane == 0 && part == 0 && T > 0) {
     S.x[env] = in.x;
     S.y[env] = in.y;
     S.th[env] = in.th;
@@ -1411,26 +1420,29 @@ __device__ __forceinline__ void roll_env(const DevState& S, int env, int lane, u
 }
 
 // Fused rollout: one launch for T steps of every env.  Waves take envs by a
-// static stride over the work order (costliest first).
+// static stride over the work order (costliest first); wpe consecutive waves
+// share an env (each fills its share of the row pairs).
 template <int MAXN, int WPB, bool ASC, int FMT>
 __global__ __launch_bounds__(64 * WPB) void k_roll(DevState S, const uint8_t* act, uint8_t* obs,
                                                    int64_t obs_stride, float* rew, uint8_t* dn,
-                                                   uint8_t* prv, int T, int store_mode) {
+                                                   uint8_t* prv, int T, int store_mode, int wpe) {
   __shared__ __align__(16) uint8_t smap[WPB][MAXN * MAXN];
   __shared__ __align__(16) uint32_t scol[WPB][2 * kMaxW];
   __shared__ uint32_t sclr[kColorWords];
   __shared__ uint32_t scvt[FMT % 3 ? 256 : 1];
   stage_tables<FMT>(sclr, scvt);
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  const int waves = (int)gridDim.x * WPB;
+  const int gw = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + w);
+  const int first = gw / wpe, part = gw - first * wpe;
+  const int stride = (int)gridDim.x * WPB / wpe;
   DevIo io{};
   io.obs = obs;
   io.mode = MODE_STEP;
   io.store_mode = store_mode;
-  for (int item = (int)blockIdx.x * WPB + w; item < S.n; item += waves) {
+  for (int item = first; item < S.n; item += stride) {
     const int env = __builtin_amdgcn_readfirstlane(S.order[item]);
     roll_env<MAXN, ASC, FMT>(S, env, lane, smap[w], sclr, scvt, scol[w], act, obs, obs_stride, rew, dn, prv, T,
-                             store_mode, io);
+                             store_mode, io, part, wpe);
   }
 }
 
@@ -1475,20 +1487,20 @@ __global__ void k_set_desc(RolloutDesc* rd, RolloutDesc v) {
 constexpr int kFmtWaves = 4;
 
 template <int MAXN, bool ASC, int FMT>
-int launch_plain_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb,
+int launch_plain_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb, int wpe,
                    hipStream_t st) {
   if constexpr (FMT != 0) {
-    const int grid = (s.n + kFmtWaves - 1) / kFmtWaves;
+    const int grid = (int)(((int64_t)s.n * wpe + kFmtWaves - 1) / kFmtWaves);
     hipLaunchKernelGGL((k_plain<MAXN, kFmtWaves, ASC, FMT>), dim3(grid), dim3(64 * kFmtWaves), 0, st, s, io,
-                       rd, t);
+                       rd, t, wpe);
     return (int)hipGetLastError();
   } else {
-    const int grid = (s.n + wpb - 1) / wpb;
+    const int grid = (int)(((int64_t)s.n * wpe + wpb - 1) / wpb);
     switch (wpb) {
-      case 1: hipLaunchKernelGGL((k_plain<MAXN, 1, ASC, 0>), dim3(grid), dim3(64), 0, st, s, io, rd, t); break;
-      case 2: hipLaunchKernelGGL((k_plain<MAXN, 2, ASC, 0>), dim3(grid), dim3(128), 0, st, s, io, rd, t); break;
-      case 4: hipLaunchKernelGGL((k_plain<MAXN, 4, ASC, 0>), dim3(grid), dim3(256), 0, st, s, io, rd, t); break;
-      case 8: hipLaunchKernelGGL((k_plain<MAXN, 8, ASC, 0>), dim3(grid), dim3(512), 0, st, s, io, rd, t); break;
+      case 1: hipLaunchKernelGGL((k_plain<MAXN, 1, ASC, 0>), dim3(grid), dim3(64), 0, st, s, io, rd, t, wpe); break;
+      case 2: hipLaunchKernelGGL((k_plain<MAXN, 2, ASC, 0>), dim3(grid), dim3(128), 0, st, s, io, rd, t, wpe); break;
+      case 4: hipLaunchKernelGGL((k_plain<MAXN, 4, ASC, 0>), dim3(grid), dim3(256), 0, st, s, io, rd, t, wpe); break;
+      case 8: hipLaunchKernelGGL((k_plain<MAXN, 8, ASC, 0>), dim3(grid), dim3(512), 0, st, s, io, rd, t, wpe); break;
       default: return -1;
     }
     return (int)hipGetLastError();
@@ -1516,17 +1528,17 @@ int launch_pipe_n(const DevState& s, const DevIo& io, const RolloutDesc* rd, int
 
 template <int MAXN, bool ASC, int FMT>
 int launch_roll_n(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride, float* rew,
-                  uint8_t* dn, uint8_t* pv, int T, int wpb, int groups, int nt, hipStream_t st) {
+                  uint8_t* dn, uint8_t* pv, int T, int wpb, int groups, int nt, int wpe, hipStream_t st) {
   if constexpr (FMT != 0) {
     hipLaunchKernelGGL((k_roll<MAXN, kFmtWaves, ASC, FMT>), dim3(groups), dim3(64 * kFmtWaves), 0, st, s, act,
-                       obs, obs_stride, rew, dn, pv, T, nt);
+                       obs, obs_stride, rew, dn, pv, T, nt, wpe);
     return (int)hipGetLastError();
   } else {
     switch (wpb) {
-      case 1: hipLaunchKernelGGL((k_roll<MAXN, 1, ASC, 0>), dim3(groups), dim3(64), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt); break;
-      case 2: hipLaunchKernelGGL((k_roll<MAXN, 2, ASC, 0>), dim3(groups), dim3(128), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt); break;
-      case 4: hipLaunchKernelGGL((k_roll<MAXN, 4, ASC, 0>), dim3(groups), dim3(256), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt); break;
-      case 8: hipLaunchKernelGGL((k_roll<MAXN, 8, ASC, 0>), dim3(groups), dim3(512), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt); break;
+      case 1: hipLaunchKernelGGL((k_roll<MAXN, 1, ASC, 0>), dim3(groups), dim3(64), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt, wpe); break;
+      case 2: hipLaunchKernelGGL((k_roll<MAXN, 2, ASC, 0>), dim3(groups), dim3(128), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt, wpe); break;
+      case 4: hipLaunchKernelGGL((k_roll<MAXN, 4, ASC, 0>), dim3(groups), dim3(256), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt, wpe); break;
+      case 8: hipLaunchKernelGGL((k_roll<MAXN, 8, ASC, 0>), dim3(groups), dim3(512), 0, st, s, act, obs, obs_stride, rew, dn, pv, T, nt, wpe); break;
       default: return -1;
     }
     return (int)hipGetLastError();
@@ -1587,8 +1599,9 @@ int by_shape(const DevState& s, int max_side, A&&... a) {
 }
 template <int MAXN, bool ASC, int FMT>
 struct PlainL {
-  static int run(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb, hipStream_t st) {
-    return launch_plain_n<MAXN, ASC, FMT>(s, io, rd, t, wpb, st);
+  static int run(const DevState& s, const DevIo& io, const RolloutDesc* rd, int t, int wpb, int wpe,
+                 hipStream_t st) {
+    return launch_plain_n<MAXN, ASC, FMT>(s, io, rd, t, wpb, wpe, st);
   }
 };
 template <int MAXN, bool ASC, int FMT>
@@ -1601,8 +1614,8 @@ struct PipeL {
 template <int MAXN, bool ASC, int FMT>
 struct RollL {
   static int run(const DevState& s, const uint8_t* act, uint8_t* obs, int64_t obs_stride, float* rew,
-                 uint8_t* dn, uint8_t* pv, int T, int wpb, int groups, int nt, hipStream_t st) {
-    return launch_roll_n<MAXN, ASC, FMT>(s, act, obs, obs_stride, rew, dn, pv, T, wpb, groups, nt, st);
+                 uint8_t* dn, uint8_t* pv, int T, int wpb, int groups, int nt, int wpe, hipStream_t st) {
+    return launch_roll_n<MAXN, ASC, FMT>(s, act, obs, obs_stride, rew, dn, pv, T, wpb, groups, nt, wpe, st);
   }
 };
 
@@ -1631,8 +1644,13 @@ int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int 
   if (s.n <= 0) return 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int wpb = lc.waves_per_group;
-  // training-buffer formats: plain form only
-  if (lc.form == 0 || s.obs_fmt != 0) return by_shape<PlainL>(s, max_side, io, rd, t, wpb, st);
+  // training-buffer formats: plain form only.  Several waves per env only for
+  // steps that write frames (resets, renders and debug records take one).
+  if (lc.form == 0 || s.obs_fmt != 0) {
+    const bool frames = io.mode == MODE_STEP && (rd != nullptr || (io.obs != nullptr && io.dbg == nullptr));
+    const int wpe = frames ? lc.waves_per_env : 1;
+    return by_shape<PlainL>(s, max_side, io, rd, t, wpb, wpe, st);
+  }
   if (lc.form == 2) {
     // waves_per_group counts wave pairs (1, 2 or 4) in the pipelined form
     const int p = wpb > 4 ? 4 : wpb;
@@ -1640,7 +1658,7 @@ int launch_batch(const DevState& s, const DevIo& io, const RolloutDesc* rd, int 
     const int need = (s.n + p - 1) / p;
     if (groups > need) groups = need;
     if (groups < 1) groups = 1;
-    if (mode_needs_plain(io, rd)) return by_shape<PlainL>(s, 64, io, rd, t, 1, st);
+    if (mode_needs_plain(io, rd)) return by_shape<PlainL>(s, 64, io, rd, t, 1, 1, st);
     return by_shape_f<PipeL, 0>(s, max_side, io, rd, t, p, groups, st);
   }
   int groups = n_cu * lc.groups_per_cu;
@@ -1681,11 +1699,12 @@ int launch_rollout_fused(const DevState& s, const uint8_t* act, uint8_t* obs, in
                                  seq, st);
   }
   const int wpb = s.obs_fmt != 0 ? kFmtWaves : lc.waves_per_group;
-  // one wave per env while they fit on the chip (16 waves per CU), else a stride
-  int groups = (s.n + wpb - 1) / wpb;
+  const int wpe = lc.waves_per_env;
+  // wpe waves per env while they fit on the chip (16 waves per CU), else a stride
+  int groups = (int)(((int64_t)s.n * wpe + wpb - 1) / wpb);
   const int cap = n_cu * (16 / wpb > 0 ? 16 / wpb : 1);
   if (groups > cap) groups = cap;
-  return by_shape<RollL>(s, max_side, act, obs, obs_stride, rew, dn, prev, T, wpb, groups, lc.store_mode, st);
+  return by_shape<RollL>(s, max_side, act, obs, obs_stride, rew, dn, prev, T, wpb, groups, lc.store_mode, wpe, st);
 }
 
 const char* kernel_error_string(int code) { return hipGetErrorString((hipError_t)code); }

@@ -52,7 +52,8 @@ class jx_env_cfg(ctypes.Structure):
 
 class jx_launch(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
-                ("groups_per_cu", ctypes.c_int32), ("store_mode", ctypes.c_int32)]
+                ("groups_per_cu", ctypes.c_int32), ("store_mode", ctypes.c_int32),
+                ("waves_per_env", ctypes.c_int32)]
 
 
 class jx_col_debug(ctypes.Structure):
@@ -341,8 +342,8 @@ class Env:
         check(lib().jx_sync(self.ctx))
 
     # -- launch mapping ----------------------------------------------------------
-    def set_launch(self, form=JX_FORM_PLAIN, waves_per_group=1, groups_per_cu=4, store_mode=0):
-        l = jx_launch(form, waves_per_group, groups_per_cu, store_mode)
+    def set_launch(self, form=JX_FORM_PLAIN, waves_per_group=1, groups_per_cu=4, store_mode=0, waves_per_env=1):
+        l = jx_launch(form, waves_per_group, groups_per_cu, store_mode, waves_per_env)
         check(lib().jx_set_launch(self.ctx, ctypes.byref(l)))
 
     def get_launch(self) -> dict:

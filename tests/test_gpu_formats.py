@@ -109,6 +109,10 @@ def _trajectory(cfg, seeds, acts, mode):
     env = U.env_of(cfg, seeds, obs=False)
     if mode == "persistent":   # a training format maps every launch form to the plain kernel
         env.set_launch(form=1, waves_per_group=2, groups_per_cu=4, store_mode=0)
+    if mode.endswith("-wpe"):   # several waves per env, each writing its share of the rows
+        env.set_launch(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0, waves_per_env=4 if
+                       mode.startswith("fused") else 2)
+        mode = mode[:-4]
     n, T, ob = len(seeds), acts.shape[0], env.obs_bytes
     acts_d = torch.from_numpy(acts).to(env.dev)
     obs = torch.zeros(T * ob, dtype=torch.uint8, device=env.dev)
@@ -149,7 +153,7 @@ def test_format_is_the_byte_frame_converted_in_every_form(base, layout, dtype):
     tab32 = np.array([orc.norm_f32(b) for b in range(256)], np.float32).view(np.uint32)
     tab16 = np.array([orc.norm_bf16(b) for b in range(256)], np.uint16)
     first = None
-    for mode in ("eager", "graph", "fused", "persistent"):
+    for mode in ("eager", "graph", "fused", "persistent", "eager-wpe", "fused-wpe"):
         out, offs_f, obf = _trajectory(cfg, seeds, acts, mode)
         if first is None:
             first = out

@@ -75,7 +75,12 @@ def test_graph_eager_persistent_identical():
                 # persistent fused rollouts: envs claimed one at a time
                 ("fused", dict(form=1, waves_per_group=4, groups_per_cu=2, store_mode=0)),
                 ("fused", dict(form=1, waves_per_group=1, groups_per_cu=1, store_mode=1)),
-                ("fused", dict(form=1, waves_per_group=8, groups_per_cu=1, store_mode=0))]
+                ("fused", dict(form=1, waves_per_group=8, groups_per_cu=1, store_mode=0)),
+                # several waves per env, each writing its share of the frame's rows
+                ("eager", dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0, waves_per_env=2)),
+                ("graph", dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=1, waves_per_env=4)),
+                ("fused", dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0, waves_per_env=4)),
+                ("fused", dict(form=0, waves_per_group=2, groups_per_cu=1, store_mode=0, waves_per_env=2))]
     _forms_equal(cfg, seeds, None, 40, launches)
 
 
@@ -107,7 +112,9 @@ def test_fused_rollout_long_and_resets():
                                          ("fused", dict(form=0, waves_per_group=8, groups_per_cu=1,
                                                         store_mode=0)),
                                          ("fused", dict(form=1, waves_per_group=4, groups_per_cu=1,
-                                                        store_mode=0))])
+                                                        store_mode=0)),
+                                         ("fused", dict(form=0, waves_per_group=4, groups_per_cu=1,
+                                                        store_mode=0, waves_per_env=2))])
 
 
 def test_shaded_fused_rollout_equals_graph_and_differs_from_unshaded():
@@ -167,7 +174,9 @@ def test_mixed_shapes_batch_identical_and_oracle():
                 ("eager", dict(form=2, waves_per_group=4, groups_per_cu=2, store_mode=1)),
                 ("fused", dict(form=0, waves_per_group=2, groups_per_cu=1, store_mode=0)),
                 ("fused", dict(form=1, waves_per_group=4, groups_per_cu=2, store_mode=0)),
-                ("fused", dict(form=1, waves_per_group=2, groups_per_cu=16, store_mode=1))]
+                ("fused", dict(form=1, waves_per_group=2, groups_per_cu=16, store_mode=1)),
+                ("fused", dict(form=0, waves_per_group=8, groups_per_cu=1, store_mode=0, waves_per_env=4)),
+                ("eager", dict(form=0, waves_per_group=4, groups_per_cu=1, store_mode=0, waves_per_env=2))]
     _forms_equal(cfgs, seeds, idx, 12, launches)
     # oracle parity of the mixed batch from shared states (render + one step)
     env = U.env_of(cfgs, seeds, idx, obs=False)
@@ -632,3 +641,19 @@ def test_persistent_step_captured_by_the_caller_replays_correctly():
         # leave the env in the replayed state for the next round
         env.set_state_bytes(got[3])
     env.close()
+
+
+def test_waves_per_env_limits():
+    """waves_per_env: 1, 2 or 4, plain form only, at most waves_per_group."""
+    from paper_2605_19926_amd import jx
+    env = U.env_of(W.TINY["cfg"], W.seeds(1, 4), obs=False)
+    for bad in (dict(form=0, waves_per_group=4, waves_per_env=3),
+                dict(form=1, waves_per_group=4, waves_per_env=2),
+                dict(form=0, waves_per_group=2, waves_per_env=4)):
+        with pytest.raises(jx.JxError) as e:
+            env.set_launch(**bad)
+        assert e.value.code == jx.JX_EINVAL
+    env.set_launch(form=0, waves_per_group=8, waves_per_env=4)
+    assert env.get_launch()["waves_per_env"] == 4
+    env.close()
+
