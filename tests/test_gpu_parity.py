@@ -242,6 +242,82 @@ def test_persistent_form_matches_plain_one_step():
     assert a >= 0
 
 
+def _fused_vs_single_full_size(wl, T, launch, n_pick, tag, stagger=False):
+    """One fused T-step launch of workload `wl` at full size under `launch`,
+    against T single-step launches from the same start (every frame compared on
+    the device, rewards, dones, final state) and, along those steps, n_pick
+    sampled envs against the oracle at every step from the shared state."""
+    import torch
+    cfg, n = wl["cfg"], wl["n_envs"]
+    H, W_ = cfg["obs_h"], cfg["obs_w"]
+    seeds = W.seeds(wl["number"], n)
+    acts = W.actions(wl["number"], T, n, cfg["n_actions"])
+    env = U.env_of(cfg, seeds, obs=False)
+    if stagger:   # every env reaches its cap inside the rollout
+        env.set_state({"t": (cfg["episode_cap"] - 1 - (np.arange(n) % T)).astype(np.uint32)})
+    env.set_launch(**launch)
+    snap = env.get_state_bytes()
+    ob = env.obs_bytes
+    act_d = torch.from_numpy(acts).to(env.dev)
+    ring = torch.empty(T * ob, dtype=torch.uint8, device=env.dev)
+    rew = torch.empty(T * n, dtype=torch.float32, device=env.dev)
+    done = torch.empty(T * n, dtype=torch.uint8, device=env.dev)
+    env.rollout(act_d, ring, rew, done, T, obs_stride=ob, graph=False, fused=True)
+    torch.cuda.synchronize()
+    fused_state = env.get_state_bytes()
+    f_rew, f_done = rew.cpu().numpy(), done.cpu().numpy()
+    env.set_state_bytes(snap)
+    env.set_launch(form=0, waves_per_group=1, groups_per_cu=1, store_mode=0)
+    one = torch.empty(ob, dtype=torch.uint8, device=env.dev)
+    r1 = torch.empty(n, dtype=torch.float32, device=env.dev)
+    d1 = torch.empty(n, dtype=torch.uint8, device=env.dev)
+    rng = np.random.default_rng(11)
+    pick = [int(i) for i in np.sort(rng.choice(n, n_pick, replace=False))]
+    grids = {i: U.oracle_maze(cfg, seeds[i]) for i in pick}
+    oc = orc.make_cfg(cfg)
+    S_prev = env.get_state()
+    stats = U.FrameStats()
+    skipped = checked = 0
+    errors = []
+    for t in range(T):
+        env.step(act_d[t], one, r1, d1)
+        torch.cuda.synchronize()
+        assert torch.equal(one, ring[t * ob:(t + 1) * ob]), f"step {t}: fused frames differ"
+        r_np, d_np = r1.cpu().numpy(), d1.cpu().numpy()
+        assert np.array_equal(r_np, f_rew[t * n:(t + 1) * n]), f"step {t}: rewards differ"
+        assert np.array_equal(d_np, f_done[t * n:(t + 1) * n]), f"step {t}: dones differ"
+        S = env.get_state()
+        one_np = one.cpu().numpy()
+        for i in pick:
+            checked += 1
+            g_after = U.gpu_state_dict(S, i)
+            skip, errs, _ = U.compare_step(U.gpu_state_dict(S_prev, i), cfg, seeds[i], grids[i], acts[t, i],
+                                           g_after, r_np[i], d_np[i], S["events"][i])
+            skipped += int(skip)
+            errors += [f"step {t} env {i}: {e}" for e in errs]
+            U.check_frame(stats, U.frame_of(one_np, env.obs_offsets, i, H, W_), grids[i], oc,
+                          orc.state_from(g_after), tag=f"step {t} env {i}")
+        S_prev = S
+    assert np.array_equal(env.get_state_bytes(), fused_state), "final state differs"
+    assert not errors, errors[:10]
+    assert skipped <= max(2, checked // 50), f"too many flagged steps: {skipped}"
+    stats.report(tag)
+    assert not stats.mismatch, stats.mismatch[:10]
+    assert stats.frac_flagged() < U.FLAG_LIMIT, stats.summary()
+    env.close()
+    return f_done
+
+
+def test_keydoor_fused_rollout_full_size():
+    """The key-door workload as bench.py times it: 8192 envs of 32x32 mazes
+    (door, key, goal and decor billboards, 84x84 frames) in one fused launch
+    with 8 waves per workgroup, every env reaching its cap inside the rollout."""
+    f_done = _fused_vs_single_full_size(W.KEYDOOR, 32, dict(form=0, waves_per_group=8, groups_per_cu=4,
+                                                            store_mode=0), 24,
+                                        f"fused-rollout/{W.KEYDOOR['name']}", stagger=True)
+    assert f_done.reshape(32, -1).any(axis=0).all(), "every env resets inside the rollout"
+
+
 def test_headline_fused_rollout_full_size():
     """The benchmark's timed configuration itself: the 4096 envs of the headline
     workload in one fused 128-step launch with 8 waves per workgroup, frames into
