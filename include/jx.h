@@ -230,7 +230,7 @@ jx_status jx_step(jx_ctx* ctx, const uint8_t* actions_dev, uint8_t* obs_dev, flo
  * Outputs (frames, rewards, dones, final state) equal T single-step launches
  * bit for bit.  Takes precedence over JX_ROLLOUT_GRAPH.  Under the plain
  * mapping, waves take envs by a static stride (waves_per_group waves per
- * workgroup); under the persistent mapping, groups_per_cu workgroups per
+ * workgroup, waves_per_env of them sharing each env); under the persistent mapping, groups_per_cu workgroups per
  * compute unit claim envs one at a time from device work queues, costliest
  * first (uneven shapes); the pipelined mapping and the training-buffer formats
  * run the static stride with 4 waves per workgroup (those formats also run
