@@ -688,7 +688,9 @@ def main() -> int:
                                   "coalesced_p50_ms": runs[0]["p50_ms"], "coalesced_p99_ms": runs[0]["p99_ms"],
                                   "plain_p50_ms": runs[1]["p50_ms"], "plain_p99_ms": runs[1]["p99_ms"],
                                   "coalesced_env_steps_per_s": runs[0]["env_steps_per_s"],
-                                  "plain_env_steps_per_s": runs[1]["env_steps_per_s"]}
+                                  "plain_env_steps_per_s": runs[1]["env_steps_per_s"],
+                                  "coalesced_device_rings_p50_ms": runs[9]["p50_ms"],
+                                  "coalesced_device_rings_p99_ms": runs[9]["p99_ms"]}
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle on the host cores)")
         line["cpu_baseline"] = cpu_baseline(wl, W.TINY)
