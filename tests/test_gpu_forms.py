@@ -388,6 +388,158 @@ def test_serving_alone_equals_mix_equals_plain():
     assert all(len(v) == T for v in results.values())
 
 
+def _alone_digests(cfg, seeds, acts, check_envs=()):
+    """A client stepped alone by plain per-step launches: per request the
+    sha256 of its frames with its rewards and dones.  For the envs in
+    check_envs every step is also checked against the oracle from the shared
+    state (the GPU's stored state before and after the step)."""
+    import hashlib
+    import torch
+    env = U.env_of(cfg, seeds, obs=False)
+    obs = torch.empty(env.obs_bytes, dtype=torch.uint8, device=env.dev)
+    oc = orc.make_cfg(cfg)
+    grids = {i: U.oracle_maze(cfg, seeds[i]) for i in check_envs}
+    stats, errors, skipped = U.FrameStats(), [], 0
+    out = []
+    for k, a in enumerate(acts):
+        before = env.get_state() if check_envs else None
+        env.step(torch.from_numpy(a).to(env.dev), obs)
+        torch.cuda.synchronize()
+        o = obs.cpu().numpy()
+        rew, done = env.reward.cpu().numpy().copy(), env.done.cpu().numpy().copy()
+        out.append((hashlib.sha256(o.tobytes()).hexdigest(), rew, done))
+        if check_envs:
+            S = env.get_state()
+            for i in check_envs:
+                g_after = U.gpu_state_dict(S, i)
+                skip, errs, _ = U.compare_step(U.gpu_state_dict(before, i), cfg, seeds[i], grids[i], a[i],
+                                               g_after, rew[i], done[i], S["events"][i])
+                skipped += int(skip)
+                errors += [f"step {k} env {i}: {e}" for e in errs]
+                g = U.frame_of(o, env.obs_offsets, i, cfg["obs_h"], cfg["obs_w"])
+                U.check_frame(stats, g, grids[i], oc, orc.state_from(g_after), tag=f"step {k} env {i}")
+    env.close()
+    return out, stats, errors, skipped
+
+
+def test_serving_trace_equals_each_client_alone():
+    """The serving workload's own recipe at a test's size: Poisson arrivals
+    (20,000 req/s offered) over 32 client slots with session churn (mean 4
+    requests), clients of 1-512 envs (log-uniform), map sides 8-64 and 64² or
+    84² frames; every fourth client has the key, door and decor sprites, every
+    third a 4-step episode cap (resets inside served launches), and every third
+    leaves its results in device rings.  The HBM budget (12 MiB) holds fewer
+    than all clients, so some wait for admission.  Requests are submitted at
+    their arrival times, each client closed right after its last request, and a
+    collector thread takes them in completion order.  Every request's frames,
+    rewards and dones equal those of the same client stepped alone by plain
+    per-step launches; on sampled envs of three clients every step of that
+    reference is checked against the oracle."""
+    import hashlib
+    import time
+    import torch
+    from paper_2605_19926_amd import jx
+    tr = W.serve_trace(360, clients=32, rate=20000.0, mean_session=4)
+    sids = list(dict.fromkeys(int(s) for s in tr["session"]))
+    count = {s: int((tr["session"] == s).sum()) for s in sids}
+    rng = np.random.default_rng(23)
+    cfgs, seeds, acts = {}, {}, {s: [] for s in sids}
+    for s in sids:
+        ob = int(tr["obs"][s])
+        kd = s % 4 == 1
+        cfgs[s] = W.env_cfg(side=int(tr["side"][s]), loop_frac=0.1, goal_sprite=1, key_door=int(kd),
+                            max_decor=2 if kd else 0, obs_h=ob, obs_w=ob,
+                            episode_cap=4 if s % 3 == 2 else 512)
+        seeds[s] = tr["seed_base"][s] + np.arange(int(tr["n_envs"][s]), dtype=np.uint64)
+    for s in tr["session"]:
+        s = int(s)
+        acts[s].append(rng.integers(0, 6, size=len(seeds[s]), dtype=np.uint8))
+    dev = {s for s in sids if s % 3 == 0}
+    # served
+    srv = jx.Server(hbm_budget=12 << 20, n_streams=4)
+    cid, rings, queued = {}, {}, 0
+    for s in sids:
+        n, fb = len(seeds[s]), cfgs[s]["obs_h"] * cfgs[s]["obs_w"] * 3
+        if s in dev:
+            rings[s] = (torch.zeros(count[s] * n * fb, dtype=torch.uint8, device="cuda"),
+                        torch.zeros(count[s] * n, dtype=torch.float32, device="cuda"),
+                        torch.zeros(count[s] * n, dtype=torch.uint8, device="cuda"))
+            cid[s], ok = srv.open_dev(seeds[s], cfgs[s], *rings[s], slots=count[s])
+        else:
+            cid[s], ok = srv.open(seeds[s], cfgs[s])
+        queued += int(not ok)
+    assert queued > 0
+    got, failures = {}, []
+
+    def collect():
+        try:
+            for _ in range(len(tr["session"])):
+                r = srv.wait_any(timeout=120.0)
+                if r is None:
+                    failures.append("a request did not complete")
+                    return
+                c, tk = r
+                res = srv.wait(c, tk)
+                got[tk] = None if res[0] is None else (hashlib.sha256(res[0].tobytes()).hexdigest(), res[1],
+                                                       res[2])
+        except jx.JxError as e:
+            failures.append(str(e))
+
+    col = threading.Thread(target=collect)
+    col.start()
+    ticket, seen = [], {s: 0 for s in sids}
+    t0 = time.perf_counter()
+    for k, s in enumerate(tr["session"]):
+        s = int(s)
+        while time.perf_counter() - t0 < tr["t"][k]:
+            pass
+        ticket.append(srv.submit(cid[s], acts[s][seen[s]]))
+        seen[s] += 1
+        if seen[s] == count[s]:
+            srv.close_client(cid[s])
+    col.join()
+    st = srv.stats()
+    srv.close()
+    assert not failures, failures
+    assert st["requests"] == len(tr["session"]) and st["launches"] < st["requests"]
+    assert st["admission_waits"] > 0 and st["failed_launches"] == 0
+    # every client alone, in the order of its requests
+    checked = {sids[0]: (), next(s for s in sids if s % 4 == 1): (), max(sids, key=lambda s: cfgs[s]["side"]): ()}
+    stats = U.FrameStats()
+    k_of = {s: 0 for s in sids}
+    ref = {}
+    for s in sids:
+        n = len(seeds[s])
+        pick = tuple(range(min(n, 6))) if s in checked else ()
+        ref[s], st_s, errs, skipped = _alone_digests(cfgs[s], seeds[s], acts[s], pick)
+        assert not errs, errs[:10]
+        assert skipped <= 2, f"client {s}: {skipped} flagged steps"
+        stats.cols += st_s.cols
+        stats.flagged += st_s.flagged
+        stats.mismatch += st_s.mismatch
+    assert not stats.mismatch, stats.mismatch[:10]
+    assert stats.cols > 0 and stats.frac_flagged() < 10 * U.FLAG_LIMIT, stats.summary()
+    n_resets = 0
+    for k, s in enumerate(tr["session"]):
+        s = int(s)
+        j = k_of[s]
+        k_of[s] += 1
+        h, rew, done = ref[s][j]
+        n_resets += int(done.sum())
+        if s in dev:
+            n, fb = len(seeds[s]), cfgs[s]["obs_h"] * cfgs[s]["obs_w"] * 3
+            o, r_, d_ = rings[s]
+            assert hashlib.sha256(o[j * n * fb:(j + 1) * n * fb].cpu().numpy().tobytes()).hexdigest() == h, \
+                f"client {s} request {j}: device-ring frames differ"
+            assert np.array_equal(r_[j * n:(j + 1) * n].cpu().numpy(), rew)
+            assert np.array_equal(d_[j * n:(j + 1) * n].cpu().numpy(), done)
+        else:
+            g = got[ticket[k]]
+            assert g[0] == h, f"client {s} request {j}: frames differ"
+            assert np.array_equal(g[1], rew) and np.array_equal(g[2], done), f"client {s} request {j}"
+    assert n_resets > 0
+
+
 def test_serving_completion_queue():
     """wait_any hands out every completed request once, in completion order,
     and the results collected through it equal those of a plain wait."""
