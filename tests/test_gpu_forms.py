@@ -388,9 +388,9 @@ def test_serving_alone_equals_mix_equals_plain():
     assert all(len(v) == T for v in results.values())
 
 
-def _alone_digests(cfg, seeds, acts, check_envs=()):
-    """A client stepped alone by plain per-step launches: per request the
-    sha256 of its frames with its rewards and dones.  For the envs in
+def _alone_digests(cfg, seeds, acts, frames=True, check_envs=()):
+    """A client stepped alone by plain per-step launches: per request its
+    rewards, dones and (if frames) the sha256 of its frames.  For the envs in
     check_envs every step is also checked against the oracle from the shared
     state (the GPU's stored state before and after the step)."""
     import hashlib
@@ -405,9 +405,9 @@ def _alone_digests(cfg, seeds, acts, check_envs=()):
         before = env.get_state() if check_envs else None
         env.step(torch.from_numpy(a).to(env.dev), obs)
         torch.cuda.synchronize()
-        o = obs.cpu().numpy()
         rew, done = env.reward.cpu().numpy().copy(), env.done.cpu().numpy().copy()
-        out.append((hashlib.sha256(o.tobytes()).hexdigest(), rew, done))
+        o = obs.cpu().numpy() if frames or check_envs else None
+        out.append((hashlib.sha256(o.tobytes()).hexdigest() if frames else None, rew, done))
         if check_envs:
             S = env.get_state()
             for i in check_envs:
@@ -422,41 +422,46 @@ def _alone_digests(cfg, seeds, acts, check_envs=()):
     return out, stats, errors, skipped
 
 
-def test_serving_trace_equals_each_client_alone():
-    """The serving workload's own recipe at a test's size: Poisson arrivals
-    (20,000 req/s offered) over 32 client slots with session churn (mean 4
-    requests), clients of 1-512 envs (log-uniform), map sides 8-64 and 64² or
-    84² frames; every fourth client has the key, door and decor sprites, every
-    third a 4-step episode cap (resets inside served launches), and every third
-    leaves its results in device rings.  The HBM budget (12 MiB) holds fewer
-    than all clients, so some wait for admission.  Requests are submitted at
-    their arrival times, each client closed right after its last request, and a
-    collector thread takes them in completion order.  Every request's frames,
-    rewards and dones equal those of the same client stepped alone by plain
-    per-step launches; on sampled envs of three clients every step of that
-    reference is checked against the oracle."""
+def _serve_trace_check(n_requests, clients, rate, mean_session, budget, variants, frame_every):
+    """Serves a trace of the serving recipe and compares every request with
+    the same client stepped alone.
+
+    Poisson arrivals at `rate` over `clients` slots with session churn (mean
+    `mean_session` requests), clients of 1-512 envs (log-uniform), map sides
+    8-64 and 64² or 84² frames (the recipe's configuration: loops 0.1, goal
+    billboard); with `variants` every fourth client also has the key, door and
+    decor sprites and every third a 4-step episode cap.  Every third client
+    leaves its results in device rings.  All clients are opened first (those
+    beyond the HBM budget wait for admission), each request is submitted at
+    its arrival time, each client is closed right after its last request, and
+    a collector thread takes requests in completion order.  Rewards and dones
+    of every request, and the frames of every request of every
+    `frame_every`-th client, must equal those of the client stepped alone by
+    plain per-step launches; on sampled envs of three clients every step of
+    that reference is checked against the oracle."""
     import hashlib
     import time
     import torch
     from paper_2605_19926_amd import jx
-    tr = W.serve_trace(360, clients=32, rate=20000.0, mean_session=4)
+    tr = W.serve_trace(n_requests, clients=clients, rate=rate, mean_session=mean_session)
     sids = list(dict.fromkeys(int(s) for s in tr["session"]))
     count = {s: int((tr["session"] == s).sum()) for s in sids}
     rng = np.random.default_rng(23)
     cfgs, seeds, acts = {}, {}, {s: [] for s in sids}
     for s in sids:
         ob = int(tr["obs"][s])
-        kd = s % 4 == 1
+        kd = variants and s % 4 == 1
         cfgs[s] = W.env_cfg(side=int(tr["side"][s]), loop_frac=0.1, goal_sprite=1, key_door=int(kd),
                             max_decor=2 if kd else 0, obs_h=ob, obs_w=ob,
-                            episode_cap=4 if s % 3 == 2 else 512)
+                            episode_cap=4 if variants and s % 3 == 2 else 512)
         seeds[s] = tr["seed_base"][s] + np.arange(int(tr["n_envs"][s]), dtype=np.uint64)
     for s in tr["session"]:
         s = int(s)
         acts[s].append(rng.integers(0, 6, size=len(seeds[s]), dtype=np.uint8))
     dev = {s for s in sids if s % 3 == 0}
+    framed = {s for k, s in enumerate(sids) if k % frame_every == 0}
     # served
-    srv = jx.Server(hbm_budget=12 << 20, n_streams=4)
+    srv = jx.Server(hbm_budget=budget, n_streams=4)
     cid, rings, queued = {}, {}, 0
     for s in sids:
         n, fb = len(seeds[s]), cfgs[s]["obs_h"] * cfgs[s]["obs_w"] * 3
@@ -468,7 +473,7 @@ def test_serving_trace_equals_each_client_alone():
         else:
             cid[s], ok = srv.open(seeds[s], cfgs[s])
         queued += int(not ok)
-    assert queued > 0
+    sid_of = {c: s for s, c in cid.items()}
     got, failures = {}, []
 
     def collect():
@@ -479,9 +484,10 @@ def test_serving_trace_equals_each_client_alone():
                     failures.append("a request did not complete")
                     return
                 c, tk = r
-                res = srv.wait(c, tk)
-                got[tk] = None if res[0] is None else (hashlib.sha256(res[0].tobytes()).hexdigest(), res[1],
-                                                       res[2])
+                want = sid_of[c] in framed
+                res = srv.wait(c, tk, want_obs=want)
+                got[tk] = None if res[1] is None else \
+                    (hashlib.sha256(res[0].tobytes()).hexdigest() if want else None, res[1], res[2])
         except jx.JxError as e:
             failures.append(str(e))
 
@@ -501,17 +507,15 @@ def test_serving_trace_equals_each_client_alone():
     st = srv.stats()
     srv.close()
     assert not failures, failures
-    assert st["requests"] == len(tr["session"]) and st["launches"] < st["requests"]
-    assert st["admission_waits"] > 0 and st["failed_launches"] == 0
+    assert st["requests"] == len(tr["session"]) and st["failed_launches"] == 0
     # every client alone, in the order of its requests
-    checked = {sids[0]: (), next(s for s in sids if s % 4 == 1): (), max(sids, key=lambda s: cfgs[s]["side"]): ()}
+    checked = {sids[0], max(sids, key=lambda s: cfgs[s]["side"]),
+               next(s for s in sids if cfgs[s]["key_door"]) if variants else sids[1]}
     stats = U.FrameStats()
-    k_of = {s: 0 for s in sids}
     ref = {}
     for s in sids:
-        n = len(seeds[s])
-        pick = tuple(range(min(n, 6))) if s in checked else ()
-        ref[s], st_s, errs, skipped = _alone_digests(cfgs[s], seeds[s], acts[s], pick)
+        pick = tuple(range(min(len(seeds[s]), 6))) if s in checked else ()
+        ref[s], st_s, errs, skipped = _alone_digests(cfgs[s], seeds[s], acts[s], s in framed, pick)
         assert not errs, errs[:10]
         assert skipped <= 2, f"client {s}: {skipped} flagged steps"
         stats.cols += st_s.cols
@@ -519,7 +523,8 @@ def test_serving_trace_equals_each_client_alone():
         stats.mismatch += st_s.mismatch
     assert not stats.mismatch, stats.mismatch[:10]
     assert stats.cols > 0 and stats.frac_flagged() < 10 * U.FLAG_LIMIT, stats.summary()
-    n_resets = 0
+    k_of = {s: 0 for s in sids}
+    n_resets = n_frames = 0
     for k, s in enumerate(tr["session"]):
         s = int(s)
         j = k_of[s]
@@ -529,15 +534,39 @@ def test_serving_trace_equals_each_client_alone():
         if s in dev:
             n, fb = len(seeds[s]), cfgs[s]["obs_h"] * cfgs[s]["obs_w"] * 3
             o, r_, d_ = rings[s]
-            assert hashlib.sha256(o[j * n * fb:(j + 1) * n * fb].cpu().numpy().tobytes()).hexdigest() == h, \
-                f"client {s} request {j}: device-ring frames differ"
-            assert np.array_equal(r_[j * n:(j + 1) * n].cpu().numpy(), rew)
-            assert np.array_equal(d_[j * n:(j + 1) * n].cpu().numpy(), done)
+            if h is not None:
+                assert hashlib.sha256(o[j * n * fb:(j + 1) * n * fb].cpu().numpy().tobytes()).hexdigest() == h, \
+                    f"client {s} request {j}: device-ring frames differ"
+            g = (h, r_[j * n:(j + 1) * n].cpu().numpy(), d_[j * n:(j + 1) * n].cpu().numpy())
         else:
             g = got[ticket[k]]
             assert g[0] == h, f"client {s} request {j}: frames differ"
-            assert np.array_equal(g[1], rew) and np.array_equal(g[2], done), f"client {s} request {j}"
-    assert n_resets > 0
+        assert np.array_equal(g[1], rew) and np.array_equal(g[2], done), f"client {s} request {j}"
+        n_frames += int(h is not None)
+    return st, queued, n_resets, n_frames
+
+
+def test_serving_trace_equals_each_client_alone():
+    """A test-size trace (360 requests at 20,000 req/s over 32 slots, mean
+    session 4, with the key-door and short-episode variants) under a 12 MiB
+    budget that holds fewer than all clients: every request's frames, rewards
+    and dones equal those of its client stepped alone."""
+    st, queued, n_resets, n_frames = _serve_trace_check(360, 32, 20000.0, 4, 12 << 20, True, 1)
+    assert queued > 0 and st["admission_waits"] > 0
+    assert st["launches"] < st["requests"]           # requests were coalesced
+    assert n_resets > 0 and n_frames == 360
+
+
+def test_serving_workload_full_size():
+    """The serving workload at its full size in the configuration the
+    benchmark times: 20,000 requests at 2000 req/s over 256 client slots (mean
+    session 64), a 64 GB budget, coalesced launches on 4 streams.  Rewards and
+    dones of every request, and every request's frames for every eighth
+    client, equal those of the client stepped alone."""
+    st, queued, n_resets, n_frames = _serve_trace_check(20_000, 256, W.SERVE["rate"], W.SERVE["mean_session"],
+                                                        64 * 10 ** 9, False, 8)
+    assert queued == 0 and st["requests"] == 20_000
+    assert n_frames > 20_000 // 16
 
 
 def test_serving_completion_queue():
