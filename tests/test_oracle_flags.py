@@ -1,9 +1,9 @@
 """Pins for the oracle's decision-window flags and its acceptance data: each
 flag is set by a state built exactly on its boundary and clear just outside
 the window, and the tie mask and the second branch mark exactly the pixels and
-the walk a tied decision can change.  The windows are the survey's readings of
-the DDA's exact ties (Sec. 2.1 marches along tile boundaries, so a ray through
-a tile corner crosses both grid lines at one parameter).  CPU only."""
+the walk a tied decision can change.  The windows are this implementation's
+reading of the DDA's exact ties (Sec. 2.1 marches along tile boundaries, so a
+ray through a tile corner crosses both grid lines at one parameter).  CPU only."""
 import math
 
 import numpy as np
