@@ -95,8 +95,8 @@ def measured_traffic(form: str, digest: str):
 def store_pattern_ceilings():
     """GB/s that constant-data store patterns reach on this device (the
     library's jx_store_ceiling program, run in its own process): the fastest
-    linear fill pattern, and the renderer's own pattern of one 64x64 frame per
-    wave and step.  None if the program is missing or fails."""
+    linear fill pattern, and the renderer's own pattern of one frame per wave
+    and step at 64x64 and at 84x84.  None if the program is missing or fails."""
     import subprocess
     exe = os.path.join(ROOT, "paper_2605_19926_amd", "jx_store_ceiling")
     if not os.path.exists(exe):
@@ -595,10 +595,12 @@ def main() -> int:
         del kobs
         r = kn * T * launches / ks
         progress(f"key-door workload: {r:.4g} env-steps/s")
+        gbs = kob * T * launches / ks / 1e9
+        ceil84 = (pattern_ceilings or {}).get("env_frames_84px_12B")
         return {"workload": kwl["name"], "steps": T * launches, "env_steps_per_s": r,
                 "ms_per_step": ks / (T * launches) * 1e3, "frame_bytes": kob // kn,
-                "obs_gbs": kob * T * launches / ks / 1e9,
-                "frac_of_hbm_peak": kob * T * launches / ks / 1e9 / HBM_PEAK_GBS}
+                "obs_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+                "frac_of_frame_pattern_ceiling": gbs / ceil84 if ceil84 else None}
 
     shaded = ascii_maps = buffers = keydoor = None
     if args.form == "fused" and slots > 1:
