@@ -180,7 +180,8 @@ void jx_destroy(jx_ctx* ctx);
  * device.  cfgs_host[n_cfgs] are the configurations, cfg_index_host[n] (NULL
  * when n_cfgs == 1) picks env i's.  Errors: JX_EINVAL for a bad configuration
  * or ASCII map (message in jx_last_error), JX_ENOMEM when the context's
- * workspace is smaller than jx_workspace_bytes(), JX_EDEVICE on a HIP error.  When obs_dev is not NULL the first frames are rendered into it.
+ * workspace is smaller than jx_workspace_bytes(), JX_EDEVICE on a HIP error.
+ * When obs_dev is not NULL the first frames are rendered into it.
  * n_envs may be 0 (every later call is then a no-op).  Synchronous: returns
  * after the reset kernel has finished. */
 jx_status jx_reset(jx_ctx* ctx, int32_t n_envs, const uint64_t* seeds_host,
@@ -219,8 +220,9 @@ jx_status jx_step(jx_ctx* ctx, const uint8_t* actions_dev, uint8_t* obs_dev, flo
  * obs_dev + t*obs_stride (obs_stride >= jx_obs_bytes(), or 0 to write every
  * step into the same frame buffer), rewards at reward_dev + t*n, dones at
  * done_dev + t*n and, when prev_action_dev is not NULL, previous actions (as in
- * jx_step) at prev_action_dev + t*n.  flags & JX_ROLLOUT_GRAPH: the T launches are captured once
- * per (T, launch mapping) into a hipGraph and replayed with one graph launch;
+ * jx_step) at prev_action_dev + t*n.  flags & JX_ROLLOUT_GRAPH: the T
+ * launches are captured once per (T, launch mapping) into a hipGraph and
+ * replayed with one graph launch;
  * the buffers of each call reach the captured kernels through a descriptor in
  * the workspace, so a captured graph serves any buffers.  Without the flag the
  * T launches are enqueued one by one. */
@@ -230,8 +232,9 @@ jx_status jx_step(jx_ctx* ctx, const uint8_t* actions_dev, uint8_t* obs_dev, flo
  * Outputs (frames, rewards, dones, final state) equal T single-step launches
  * bit for bit.  Takes precedence over JX_ROLLOUT_GRAPH.  Under the plain
  * mapping, waves take envs by a static stride (waves_per_group waves per
- * workgroup, waves_per_env of them sharing each env); under the persistent mapping, groups_per_cu workgroups per
- * compute unit claim envs one at a time from device work queues, costliest
+ * workgroup, waves_per_env of them sharing each env); under the persistent
+ * mapping, groups_per_cu workgroups per compute unit claim envs one at a time
+ * from device work queues, costliest
  * first (uneven shapes); the pipelined mapping and the training-buffer formats
  * run the static stride with 4 waves per workgroup (those formats also run
  * every per-step launch in the plain form). */
@@ -322,8 +325,9 @@ typedef struct jx_server jx_server;
  * maps.  Testing hook: when the environment variable JX_SERVER_FAIL_LAUNCH
  * holds an integer k >= 0 at creation, the server's k-th launch (0-based, in
  * issue order) is treated as failed without any HIP call being made for it, so
- * the failure path below can be exercised with every kernel exiting normally.  Each stream also holds a 128 MiB device staging buffer for its
- * launches (descriptors, actions, results), and the server a pinned host arena
+ * the failure path below can be exercised with every kernel exiting normally.
+ * Each stream also holds a 128 MiB device staging buffer for its launches
+ * (descriptors, actions, results), and the server a pinned host arena
  * of min(budget, 2 GiB) mirroring it; one step of a client must fit both.
  * n_streams 1..8.  max_batch_envs bounds envs per launch (0 = no bound). */
 jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_bytes,
