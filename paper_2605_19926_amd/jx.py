@@ -130,6 +130,12 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2605_19926_amd.build`")
+        # torch bundles its own HIP runtime under the same soname as the
+        # system's.  Loaded first, it satisfies libjx.so's dependency, so the
+        # process holds one HIP runtime and torch's device memory and streams
+        # are valid in the library's calls.  Loaded after libjx.so, torch would
+        # bring a second runtime that cannot open the GPU.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             if not hasattr(L, name):

@@ -148,3 +148,23 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before torch must not leave two HIP runtimes in the
+    process (torch's own and the system's, under one soname): the binding loads
+    torch first, so libjx.so binds to torch's runtime.  Checked in a fresh
+    interpreter from the memory map; no device is touched."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2605_19926_amd import jx\n"
+            "jx.lib()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(sorted({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=root)
+    assert r.returncode == 0, r.stderr[-2000:]
+    import ast
+    libs = ast.literal_eval(r.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
