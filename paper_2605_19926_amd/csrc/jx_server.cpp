@@ -197,6 +197,9 @@ struct jx_server {
 
   std::mutex mu;
   std::condition_variable cv_sched;   // scheduler: new work / stream freed / stop
+  // Bumped, with mu held, at every change that can give the scheduler work; an
+  // idle scheduler polls it before sleeping on cv_sched (see sched_idle).
+  std::atomic<uint64_t> sched_epoch{0};
   std::condition_variable cv_admit;   // admitter: a client queued / memory freed / stop
   std::condition_variable cv_done;    // waiters: a request completed
   std::condition_variable cv_comp;    // completion thread: a launch was issued
@@ -216,6 +219,12 @@ struct jx_server {
   jx_server_stats stats{};
   std::thread sched, comp, admitter;
 };
+
+// Tells the scheduler there may be new work; call with s->mu held.
+void wake_sched(jx_server* s) {
+  s->sched_epoch.fetch_add(1, std::memory_order_release);
+  s->cv_sched.notify_one();
+}
 
 namespace {
 
@@ -346,7 +355,7 @@ void admitter_main(jx_server* s) {
     }
     c->st = ACTIVE;
     s->stats.clients_active += 1;
-    s->cv_sched.notify_one();
+    wake_sched(s);
   }
 }
 
@@ -490,13 +499,31 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
     s->stats.failed_launches += 1;
     ss.busy = false;
     s->cv_done.notify_all();
-    s->cv_sched.notify_one();
+    wake_sched(s);
     return;
   }
   s->stats.launches += 1;
   s->stats.env_steps += n_items;
   s->inflight.push_back(std::move(L));
   s->cv_comp.notify_one();
+}
+
+// An idle scheduler polls the wake counter for up to kSchedSpin without the
+// lock, so that a request arriving then is picked up within about a
+// microsecond instead of after a thread wake-up (about 10 us here), and then
+// sleeps until the counter moves.  Every bump happens with the lock held, and
+// the counter is read under it before the sleep, so no wake-up is lost.  The
+// polling keeps one host core busy while requests arrive less than kSchedSpin
+// apart (at 2000 requests/s, 86% of Poisson gaps are shorter than 1 ms).
+constexpr auto kSchedSpin = std::chrono::microseconds(1000);
+void sched_idle(jx_server* s, std::unique_lock<std::mutex>& lk) {
+  const uint64_t seen = s->sched_epoch.load(std::memory_order_acquire);
+  lk.unlock();
+  const auto until = std::chrono::steady_clock::now() + kSchedSpin;
+  while (s->sched_epoch.load(std::memory_order_acquire) == seen && std::chrono::steady_clock::now() < until)
+    std::this_thread::yield();
+  lk.lock();
+  s->cv_sched.wait(lk, [&] { return s->stop || s->sched_epoch.load(std::memory_order_acquire) != seen; });
 }
 
 void scheduler_main(jx_server* s) {
@@ -519,7 +546,7 @@ void scheduler_main(jx_server* s) {
       }
     }
     if (ready.empty() || k < 0) {
-      s->cv_sched.wait(lk);
+      sched_idle(s, lk);
       continue;
     }
     std::sort(ready.begin(), ready.end(), [](Client* a, Client* b) {
@@ -548,7 +575,7 @@ void scheduler_main(jx_server* s) {
       batch.resize(batch.size() / 2);
     }
     if (batch.empty()) {
-      s->cv_sched.wait(lk);
+      sched_idle(s, lk);
       continue;
     }
     s->next_stream = (k + 1) % (int)s->streams.size();
@@ -602,7 +629,7 @@ void completion_main(jx_server* s) {
     }
     if (retired) {
       s->cv_done.notify_all();
-      s->cv_sched.notify_one();
+      wake_sched(s);
     } else {
       // nothing finished yet: poll again shortly (launches take tens of
       // microseconds and up)
@@ -680,6 +707,7 @@ void jx_server_destroy(jx_server* s) {
   {
     std::lock_guard<std::mutex> g(s->mu);
     s->stop = true;
+    s->sched_epoch.fetch_add(1, std::memory_order_release);
   }
   s->cv_sched.notify_all();
   s->cv_comp.notify_all();
@@ -778,7 +806,7 @@ jx_status open_client(jx_server* s, int32_t n_envs, const uint64_t* seeds, const
   }
   cp->st = ACTIVE;
   s->stats.clients_active += 1;
-  s->cv_sched.notify_one();
+  wake_sched(s);
   return JX_OK;
 }
 
@@ -819,7 +847,7 @@ jx_status jx_server_submit(jx_server* s, int32_t client, const uint8_t* actions,
   c->queue.push_back(r);
   s->requests[r->ticket] = r;
   *ticket = r->ticket;
-  s->cv_sched.notify_one();
+  wake_sched(s);
   return JX_OK;
 }
 
@@ -856,6 +884,7 @@ jx_status jx_server_wait(jx_server* s, uint64_t ticket, double timeout_s, uint8_
   {
     std::lock_guard<std::mutex> g(s->mu);
     release_staging(s, r.get());
+    s->sched_epoch.fetch_add(1, std::memory_order_release);
   }
   s->cv_sched.notify_one();
   if (failed)
@@ -902,7 +931,7 @@ jx_status jx_server_close(jx_server* s, int32_t client) {
     // its queued requests have run
     c->closing = true;
   }
-  s->cv_sched.notify_one();
+  wake_sched(s);
   return JX_OK;
 }
 
