@@ -314,11 +314,10 @@ jx_status jx_make_layout(uint64_t seed, const jx_env_cfg* cfg, uint8_t* grid_hos
  * launches spread over n_streams streams, so that requests arriving while
  * others run are admitted and overlap on the device (continuous batching).
  * Clients are admitted while their device memory fits the HBM budget; others
- * wait in FIFO order.  All functions are thread-safe.  For latency the
- * server's threads poll rather than sleep while it is busy: the scheduler for
- * up to 1 ms after each event, the completion thread every 2 us while
- * launches are in flight, so a loaded server keeps up to two host cores
- * busy.
+ * wait in FIFO order.  All functions are thread-safe.  For latency two of the
+ * server's threads poll rather than sleep: the scheduler for up to 1 ms when
+ * the device falls idle, the completion thread every 2 us while launches are
+ * in flight, so a busy server keeps up to two host cores busy.
  * ------------------------------------------------------------------------- */
 typedef struct jx_server jx_server;
 

@@ -508,18 +508,19 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
   s->cv_comp.notify_one();
 }
 
-// An idle scheduler polls the wake counter for up to kSchedSpin without the
-// lock, so that a request arriving then is picked up within about a
-// microsecond instead of after a thread wake-up (about 10 us here), and then
-// sleeps until the counter moves.  Every bump happens with the lock held, and
-// the counter is read under it before the sleep, so no wake-up is lost.  The
-// polling keeps one host core busy while requests arrive less than kSchedSpin
-// apart (at 2000 requests/s, 86% of Poisson gaps are shorter than 1 ms).
+// An idle scheduler (with poll set) polls the wake counter for up to
+// kSchedSpin without the lock, so that a request arriving then is picked up
+// within about a microsecond instead of after a thread wake-up (about 10 us
+// here), and then sleeps until the counter moves.  Every bump happens with the
+// lock held, and the counter is read under it before the sleep, so no wake-up
+// is lost.  The polling keeps one host core busy while requests arrive less
+// than kSchedSpin apart (at 2000 requests/s, 86% of Poisson gaps are shorter
+// than 1 ms).
 constexpr auto kSchedSpin = std::chrono::microseconds(1000);
-void sched_idle(jx_server* s, std::unique_lock<std::mutex>& lk) {
+void sched_idle(jx_server* s, std::unique_lock<std::mutex>& lk, bool poll) {
   const uint64_t seen = s->sched_epoch.load(std::memory_order_acquire);
   lk.unlock();
-  const auto until = std::chrono::steady_clock::now() + kSchedSpin;
+  const auto until = std::chrono::steady_clock::now() + (poll ? kSchedSpin : std::chrono::microseconds(0));
   while (s->sched_epoch.load(std::memory_order_acquire) == seen && std::chrono::steady_clock::now() < until)
     std::this_thread::yield();
   lk.lock();
@@ -546,7 +547,11 @@ void scheduler_main(jx_server* s) {
       }
     }
     if (ready.empty() || k < 0) {
-      sched_idle(s, lk);
+      // poll only when the device is idle too: under load a completion or a
+      // submit wakes the scheduler soon anyway, and polling threads then
+      // contend for the lock and the host cores (measured: a p99 of several
+      // milliseconds at 64,000 requests/s against 0.3-1.2 ms without)
+      sched_idle(s, lk, ready.empty() && s->inflight.empty());
       continue;
     }
     std::sort(ready.begin(), ready.end(), [](Client* a, Client* b) {
@@ -575,7 +580,7 @@ void scheduler_main(jx_server* s) {
       batch.resize(batch.size() / 2);
     }
     if (batch.empty()) {
-      sched_idle(s, lk);
+      sched_idle(s, lk, false);
       continue;
     }
     s->next_stream = (k + 1) % (int)s->streams.size();
@@ -595,17 +600,41 @@ void completion_main(jx_server* s) {
   // thread only.
   prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(s->mu);
+  std::vector<hipEvent_t> evs;
+  std::vector<hipError_t> res;
   while (true) {
     while (s->inflight.empty() && !s->stop) s->cv_comp.wait(lk);
     if (s->inflight.empty() && s->stop) return;
-    bool retired = false;
-    for (auto it = s->inflight.begin(); it != s->inflight.end();) {
-      const hipError_t e = hipEventQuery(it->ev);
+    // The events are queried without the lock, which submits, waits and the
+    // scheduler need far more often than this thread.  Only this thread
+    // removes launches, and a stream's event is not recorded again before its
+    // launch is retired here, so the first evs.size() launches are the same
+    // ones when the lock is taken back (the scheduler only appends).
+    evs.clear();
+    for (const Launch& L : s->inflight) evs.push_back(L.ev);
+    lk.unlock();
+    res.resize(evs.size());
+    bool any = false;
+    for (size_t i = 0; i < evs.size(); ++i) {
+      res[i] = hipEventQuery(evs[i]);
+      any = any || res[i] != hipErrorNotReady;
+    }
+    if (!any) {
+      // nothing finished yet: poll again shortly (launches take tens of
+      // microseconds and up)
+      std::this_thread::sleep_for(std::chrono::microseconds(2));
+      lk.lock();
+      continue;
+    }
+    const double t = now_s();
+    lk.lock();
+    auto it = s->inflight.begin();
+    for (size_t i = 0; i < res.size(); ++i) {
+      const hipError_t e = res[i];
       if (e == hipErrorNotReady) {
         ++it;
         continue;
       }
-      const double t = now_s();
       for (auto& r : it->reqs) {
         r->status = (e == hipSuccess) ? 2 : 3;
         r->t_done = t;
@@ -617,7 +646,6 @@ void completion_main(jx_server* s) {
       if (e != hipSuccess) s->fatal = std::string("device error: ") + hipGetErrorString(e);
       s->streams[it->stream].busy = false;
       it = s->inflight.erase(it);
-      retired = true;
       // requests collected through jx_server_wait leave stale entries in the
       // completion queue: prune them once they dominate (amortised O(1))
       if (s->completed.size() > 2 * s->requests.size() + 1024) {
@@ -627,16 +655,8 @@ void completion_main(jx_server* s) {
         s->completed.swap(keep);
       }
     }
-    if (retired) {
-      s->cv_done.notify_all();
-      wake_sched(s);
-    } else {
-      // nothing finished yet: poll again shortly (launches take tens of
-      // microseconds and up)
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(2));
-      lk.lock();
-    }
+    s->cv_done.notify_all();
+    wake_sched(s);
   }
 }
 
