@@ -200,6 +200,10 @@ struct jx_server {
   // Bumped, with mu held, at every change that can give the scheduler work; an
   // idle scheduler polls it before sleeping on cv_sched (see sched_idle).
   std::atomic<uint64_t> sched_epoch{0};
+  // Launches appended to `inflight` so far (bumped under mu): the completion
+  // thread polls its snapshot of the in-flight events without the lock until
+  // this moves or one of them completes.
+  std::atomic<uint64_t> launches_pushed{0};
   std::condition_variable cv_admit;   // admitter: a client queued / memory freed / stop
   std::condition_variable cv_done;    // waiters: a request completed
   std::condition_variable cv_comp;    // completion thread: a launch was issued
@@ -505,6 +509,7 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
   s->stats.launches += 1;
   s->stats.env_steps += n_items;
   s->inflight.push_back(std::move(L));
+  s->launches_pushed.fetch_add(1, std::memory_order_release);
   s->cv_comp.notify_one();
 }
 
@@ -606,23 +611,28 @@ void completion_main(jx_server* s) {
     while (s->inflight.empty() && !s->stop) s->cv_comp.wait(lk);
     if (s->inflight.empty() && s->stop) return;
     // The events are queried without the lock, which submits, waits and the
-    // scheduler need far more often than this thread.  Only this thread
+    // scheduler need far more often than this thread (taking it at every poll
+    // pushed the 64,000 requests/s p99 from 0.2 to 1-2.5 ms).  Only this thread
     // removes launches, and a stream's event is not recorded again before its
     // launch is retired here, so the first evs.size() launches are the same
     // ones when the lock is taken back (the scheduler only appends).
     evs.clear();
     for (const Launch& L : s->inflight) evs.push_back(L.ev);
+    const uint64_t pushed = s->launches_pushed.load(std::memory_order_acquire);
     lk.unlock();
     res.resize(evs.size());
+    // poll the snapshot every 2 us (launches take tens of microseconds and up)
+    // without touching the lock, until a launch completes or a new one starts
     bool any = false;
-    for (size_t i = 0; i < evs.size(); ++i) {
-      res[i] = hipEventQuery(evs[i]);
-      any = any || res[i] != hipErrorNotReady;
+    while (true) {
+      for (size_t i = 0; i < evs.size(); ++i) {
+        res[i] = hipEventQuery(evs[i]);
+        any = any || res[i] != hipErrorNotReady;
+      }
+      if (any || s->launches_pushed.load(std::memory_order_acquire) != pushed) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(2));
     }
     if (!any) {
-      // nothing finished yet: poll again shortly (launches take tens of
-      // microseconds and up)
-      std::this_thread::sleep_for(std::chrono::microseconds(2));
       lk.lock();
       continue;
     }
