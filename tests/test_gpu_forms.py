@@ -557,13 +557,16 @@ def test_serving_trace_equals_each_client_alone():
     assert n_resets > 0 and n_frames == 360
 
 
-def test_serving_workload_full_size():
+@pytest.mark.parametrize("rate", [W.SERVE["rate"], 64_000.0], ids=["2000rps", "64000rps"])
+def test_serving_workload_full_size(rate):
     """The serving workload at its full size in the configuration the
-    benchmark times: 20,000 requests at 2000 req/s over 256 client slots (mean
-    session 64), a 64 GB budget, coalesced launches on 4 streams.  Rewards and
-    dones of every request, and every request's frames for every eighth
-    client, equal those of the client stepped alone."""
-    st, queued, n_resets, n_frames = _serve_trace_check(20_000, 256, W.SERVE["rate"], W.SERVE["mean_session"],
+    benchmark times: 20,000 requests at 2000 req/s (and at 64,000 req/s, the
+    benchmark's highest offered load, where launches overlap on every stream)
+    over 256 client slots (mean session 64), a 64 GB budget, coalesced
+    launches on 4 streams.  Rewards and dones of every request, and every
+    request's frames for every eighth client, equal those of the client
+    stepped alone."""
+    st, queued, n_resets, n_frames = _serve_trace_check(20_000, 256, rate, W.SERVE["mean_session"],
                                                         64 * 10 ** 9, False, 8)
     assert queued == 0 and st["requests"] == 20_000
     assert n_frames > 20_000 // 16
