@@ -329,9 +329,11 @@ typedef struct jx_server jx_server;
  * holds an integer k >= 0 at creation, the server's k-th launch (0-based, in
  * issue order) is treated as failed without any HIP call being made for it, so
  * the failure path below can be exercised with every kernel exiting normally.
- * Each stream also holds a 128 MiB device staging buffer for its launches
- * (descriptors, actions, results), and the server a pinned host arena
- * of min(budget, 2 GiB) mirroring it; one step of a client must fit both.
+ * Each stream also holds a 128 MiB device staging buffer for its launches'
+ * descriptors and actions, and the server a pinned host arena of
+ * min(budget, 2 GiB) from which they are copied and into which the serving
+ * kernels write host clients' results directly; one step of a client must
+ * fit both.
  * n_streams 1..8.  max_batch_envs bounds envs per launch (0 = no bound). */
 jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_bytes,
                            int32_t n_streams, int32_t mode, int32_t max_batch_envs);

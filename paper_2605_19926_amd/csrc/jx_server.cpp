@@ -10,12 +10,13 @@
 //   scheduler       packs every ready request (its client has no step in
 //                   flight, its results fit the staging buffers) into one
 //                   launch on the next free stream.  A launch's descriptors,
-//                   work items, actions and results sit in one range of that
-//                   stream's device staging buffer, mirrored by one range of
-//                   the pinned host arena, so a launch is one H2D copy, the
-//                   serving kernel, one D2H copy and an event, whatever the
-//                   number of clients in it; the HIP calls are made without
-//                   the server lock
+//                   work items and actions sit in one range of the pinned
+//                   host arena, copied to the same range of that stream's
+//                   device staging buffer, and the kernel writes the results
+//                   of host-result clients straight into the pinned range, so
+//                   a launch is one H2D copy, the serving kernel and an
+//                   event, whatever the number of clients in it; the HIP calls
+//                   are made without the server lock
 //   completion      polls the in-flight launches and retires each as it
 //                   completes (any stream order), stamping its requests
 // A caller's wait copies a request's results out of the staging arena and
@@ -183,6 +184,7 @@ constexpr int64_t kStagingMaxBytes = int64_t(2) << 30;
 struct jx_server {
   int device = 0;
   uint8_t* host_base = nullptr;  // pinned staging arena
+  uint8_t* host_dev = nullptr;   // its device view: the serving kernels write host clients' results there
   int64_t host_bytes = 0;
   Arena host;
   int mode = JX_SERVE_COALESCE;
@@ -394,6 +396,7 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
   L.stream = k;
   L.ev = ss.ev;
   uint8_t* h = s->host_base + host_off;
+  uint8_t* hd = s->host_dev + host_off;
   uint8_t* d = ss.d_stage;
   auto range = std::make_shared<StageRange>();
   range->off = host_off;
@@ -424,9 +427,14 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
       r->h_obs = h + P.obs[j];
       r->h_rew = (float*)(h + P.rew[j]);
       r->h_done = h + P.done[j];
-      io.obs = d + P.obs[j];
-      io.rew = reinterpret_cast<float*>(d + P.rew[j]);
-      io.done = d + P.done[j];
+      // the kernel writes the results straight into the pinned range (through
+      // its device view), where jx_server_wait copies them out: no device
+      // staging and no copy back (measured: the median at 2000 req/s fell
+      // from 0.064 to 0.046 ms and at 8000 req/s from 0.091 to 0.066 ms,
+      // with the saturated rate unchanged)
+      io.obs = hd + P.obs[j];
+      io.rew = reinterpret_cast<float*>(hd + P.rew[j]);
+      io.done = hd + P.done[j];
     }
     c->launched += 1;
     dev_io[j] = io;
@@ -472,11 +480,6 @@ void issue(jx_server* s, std::unique_lock<std::mutex>& lk, int k, const std::vec
                                groups, st) == 0;
       ok = ran;
     }
-    // results of host-result clients back to the pinned range (none when every
-    // client of the launch keeps its results on the device)
-    if (P.total > P.results)
-      ok = ok && hipMemcpyAsync(h + P.results, d + P.results, (size_t)(P.total - P.results),
-                                hipMemcpyDeviceToHost, st) == hipSuccess;
     ok = ok && hipEventRecord(ss.ev, st) == hipSuccess;
     // a launch that failed part-way may still have work queued on the stream:
     // drain it before the slot and the staging range can be reused
@@ -713,6 +716,7 @@ jx_status jx_server_create(jx_server** out, int32_t device, size_t hbm_budget_by
   s->arena.init((int64_t)hbm_budget_bytes);
   s->host_bytes = std::min<int64_t>((int64_t)hbm_budget_bytes, kStagingMaxBytes);
   SRV_CHK(hipHostMalloc((void**)&s->host_base, (size_t)s->host_bytes), "pinned staging allocation failed");
+  SRV_CHK(hipHostGetDevicePointer((void**)&s->host_dev, s->host_base, 0), "pinned staging device view failed");
   s->host.init(s->host_bytes);
   SRV_CHK(hipStreamCreateWithFlags(&s->admin, hipStreamNonBlocking), "stream");
   const int ns = (mode == JX_SERVE_PLAIN) ? 1 : n_streams;
